@@ -1,0 +1,678 @@
+/*
+ * oracle.c -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, FP64 CPU implementation of the free-energy lattice Boltzmann
+ * step analysed by Pooley & Furtado, "Eliminating spurious velocities in the
+ * free energy lattice Boltzmann method".  It exists to check the GPU library;
+ * only the tests, the smoke check and the benchmark's CPU-baseline leg may
+ * load it.  It shares no source, header, table or helper with the GPU
+ * library, and the GPU library never calls it.
+ *
+ * The method is an explicit iteration, so this file takes its steps in the
+ * paper's order and notation:
+ *   moments                     Section "Model", Eq. (rho)
+ *   gradient / Laplacian        Eqs. (xderiv), (laplace); 3D Eq. (laplacian3d)
+ *   van der Waals bulk pressure Eq. (p0); c_s^2 = dp0/drho, Appendix A
+ *   lambda term                 Eq. (viscous)
+ *   equilibrium                 Eq. (equilibrium), Eq. (feq0)
+ *   body force (forcing scheme) Section "Using a forcing method"
+ *   BGK collision + streaming   Eq. (latbolt)
+ *
+ * State representation: f[i][z][y][x] holds f_i(r,t), the population at
+ * site r after streaming (the paper's f_i(r,t)).  All arrays are SoA with x
+ * fastest.  Every boundary is periodic.  Units: dx = dt = c = 1.
+ *
+ * Readings of the paper taken here (each is listed with its justification in
+ * the design notes of the repository):
+ *  - the rest equilibrium is f0eq = rho - sum_{i>=1} f_i^eq (the printed
+ *    "f_i" would make the definition vacuous; mass moment, Appendix A);
+ *  - the w^t term carries kappa (Eq. (pt) and the kappa rho lap rho stencil
+ *    label in Eq. (expand2));
+ *  - w^xy_i = +1/4 on e5,e6 and -1/4 on e7,e8 (the constraint list after
+ *    Eq. (fi)); the summary's "w^xy_5-8 = 1/4" loses the sign;
+ *  - D3Q19: w_1-6 = w^p_1-6 = w^t_1-6 = 1/6 and w^xx_1,2 = w^yy_3,4 =
+ *    w^zz_5,6 = 5/12 (the printed 1/3 values violate the second-moment
+ *    condition of Appendix A and the stated reduction to 2D);
+ *  - 3D body force g_a = -d_b (M_ab - delta_ab M_gg / 2), the kappa part of
+ *    Eq. (pt), with the 3D gradient stencil;
+ *  - the rest forcing term is F_0 = -sum_{i>=1} F_i (zeroth forcing moment);
+ *  - the equilibrium and forcing use u = j / rho; the reported velocity of
+ *    the forcing scheme is v = u + g / (2 rho) (end of Appendix A).
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef struct {
+    int q;          /* 9 = D2Q9, 19 = D3Q19 */
+    int scheme;     /* 0 = tuned equilibrium, 1 = momentum-conserving force */
+    int nx, ny, nz; /* nz = 1 for D2Q9 */
+    int lambda_on;  /* 1 = include the Galilean-invariance lambda terms */
+    double a, b, T, kappa, tau;
+    double B;       /* gradient stencil: off-axis coefficient */
+    double D;       /* Laplacian stencil: off-axis coefficient */
+    double F;       /* force stencil: off-axis coefficient */
+    double wp_d, wt_d, wxx_d; /* D2Q9 equilibrium weights on the diagonals */
+} orc_params;
+
+/* ---- velocity sets ------------------------------------------------------ */
+
+/* D2Q9 numbering of Section "Model": e1,2 = (+-1,0), e3,4 = (0,+-1),
+ * e5,6 = (+-1,+-1), e7,8 = (-+1,+-1). */
+static const int E2[9][3] = {
+    {0, 0, 0}, {1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0},
+    {1, 1, 0}, {-1, -1, 0}, {-1, 1, 0}, {1, -1, 0}};
+
+/* D3Q19 numbering of Section "Extension to 3D": faces e1..e6, then the
+ * twelve square diagonals e7..e18 column by column as printed. */
+static const int E3[19][3] = {
+    {0, 0, 0},
+    {1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1},
+    {1, 1, 0}, {-1, 1, 0}, {1, -1, 0}, {-1, -1, 0},
+    {0, 1, 1}, {0, -1, 1}, {0, 1, -1}, {0, -1, -1},
+    {1, 0, 1}, {-1, 0, 1}, {1, 0, -1}, {-1, 0, -1}};
+
+typedef struct {
+    int q, dim;
+    int e[19][3];
+    double w[19], wp[19], wt[19];
+    double wm[6][19]; /* M-term weights: xx, yy, zz, xy, yz, zx */
+    /* stencils as 3x3x3 arrays [slice][row][col]: slice 0,1,2 = z+1,z,z-1;
+     * row 0,1,2 = y+1,y,y-1; col 0,1,2 = x-1,x,x+1 (the paper's layout) */
+    double gx[3][3][3], gy[3][3][3], gz[3][3][3], lap[3][3][3];
+    double fx[3][3][3], fy[3][3][3], fz[3][3][3];
+} tables;
+
+static void zero3(double s[3][3][3]) { memset(s, 0, sizeof(double) * 27); }
+
+/* Build the gradient stencils of Eq. (xderiv) (2D) or Eq. (laplacian3d) (3D)
+ * for the x direction with on-axis coefficient A and off-axis coefficient B,
+ * then obtain y and z by rotating the lattice. */
+static void build_gradient(int dim, double A, double B,
+                           double sx[3][3][3], double sy[3][3][3], double sz[3][3][3])
+{
+    zero3(sx); zero3(sy); zero3(sz);
+    if (dim == 2) {
+        /* d_x = [ -B 0 B ; -A 0 A ; -B 0 B ] in the z = 0 slice */
+        double m[3][3] = {{-B, 0, B}, {-A, 0, A}, {-B, 0, B}};
+        for (int r = 0; r < 3; r++)
+            for (int c = 0; c < 3; c++) {
+                sx[1][r][c] = m[r][c];
+                /* d_y: x and y interchanged, i.e. the stencil transposed so
+                 * that the top row (y+1) carries +B +A +B */
+                sy[1][r][c] = m[2 - c][2 - r];
+            }
+        return;
+    }
+    /* 3D: z = +-1 slices carry only (-B 0 B) on the middle row; the z = 0
+     * slice is the full 2D pattern. */
+    for (int s = 0; s < 3; s++)
+        for (int r = 0; r < 3; r++)
+            for (int c = 0; c < 3; c++) {
+                int dx = c - 1, dy = 1 - r, dz = 1 - s;
+                int nnz = (dx != 0) + (dy != 0) + (dz != 0);
+                /* x-derivative: odd in dx, touches faces (A) and edges (B) */
+                if (dx != 0 && nnz == 1) sx[s][r][c] = A * dx;
+                if (dx != 0 && nnz == 2) sx[s][r][c] = B * dx;
+                if (dy != 0 && nnz == 1) sy[s][r][c] = A * dy;
+                if (dy != 0 && nnz == 2) sy[s][r][c] = B * dy;
+                if (dz != 0 && nnz == 1) sz[s][r][c] = A * dz;
+                if (dz != 0 && nnz == 2) sz[s][r][c] = B * dz;
+            }
+}
+
+static void build_laplacian(int dim, double C, double D, double s[3][3][3])
+{
+    zero3(s);
+    if (dim == 2) {
+        double m[3][3] = {{D, C, D}, {C, -4.0 * (C + D), C}, {D, C, D}};
+        for (int r = 0; r < 3; r++)
+            for (int c = 0; c < 3; c++) s[1][r][c] = m[r][c];
+        return;
+    }
+    double E = -6.0 * C - 12.0 * D;
+    double top[3][3] = {{0, D, 0}, {D, C, D}, {0, D, 0}};
+    double mid[3][3] = {{D, C, D}, {C, E, C}, {D, C, D}};
+    for (int r = 0; r < 3; r++)
+        for (int c = 0; c < 3; c++) {
+            s[0][r][c] = top[r][c];
+            s[1][r][c] = mid[r][c];
+            s[2][r][c] = top[r][c];
+        }
+}
+
+static void build_tables(const orc_params *p, tables *t)
+{
+    memset(t, 0, sizeof(*t));
+    t->q = p->q;
+    t->dim = (p->q == 9) ? 2 : 3;
+    if (t->dim == 2) {
+        memcpy(t->e, E2, sizeof(E2));
+        for (int i = 1; i <= 8; i++) t->w[i] = (i <= 4) ? 1.0 / 3.0 : 1.0 / 12.0;
+        /* constraints after Eq. (fi): 2 w_1-4 + 4 w_5-8 = 1 for p and t;
+         * 2 w^xx_1-2 + 4 w^xx_5-8 = 1/2, 2 w^yy_1-2 + 4 w^yy_5-8 = -1/2,
+         * x <-> y symmetry, w^xy_1-4 = 0, w^xy_5-6 = 1/4, w^xy_7-8 = -1/4 */
+        for (int i = 1; i <= 8; i++) {
+            int diag = (i >= 5);
+            t->wp[i] = diag ? p->wp_d : 0.5 - 2.0 * p->wp_d;
+            t->wt[i] = diag ? p->wt_d : 0.5 - 2.0 * p->wt_d;
+            if (diag) {
+                t->wm[0][i] = p->wxx_d;
+                t->wm[1][i] = p->wxx_d;
+                t->wm[3][i] = (i <= 6) ? 0.25 : -0.25;
+            } else if (i <= 2) {
+                t->wm[0][i] = 0.25 - 2.0 * p->wxx_d;
+                t->wm[1][i] = -0.25 - 2.0 * p->wxx_d;
+            } else {
+                t->wm[0][i] = -0.25 - 2.0 * p->wxx_d;
+                t->wm[1][i] = 0.25 - 2.0 * p->wxx_d;
+            }
+        }
+        double A = (1.0 - 4.0 * p->B) / 2.0;  /* 2A + 4B = 1 */
+        double C = 1.0 - 2.0 * p->D;          /* C + 2D = 1 */
+        double Ef = (1.0 - 4.0 * p->F) / 2.0; /* force stencil, same form */
+        build_gradient(2, A, p->B, t->gx, t->gy, t->gz);
+        build_laplacian(2, C, p->D, t->lap);
+        build_gradient(2, Ef, p->F, t->fx, t->fy, t->fz);
+        return;
+    }
+    memcpy(t->e, E3, sizeof(E3));
+    /* Eq. (3dres), with w_1-6 = 1/6 and the axial w^aa = 5/12 readings */
+    for (int i = 1; i <= 18; i++) {
+        t->w[i] = (i <= 6) ? 1.0 / 6.0 : 1.0 / 12.0;
+        t->wp[i] = t->w[i];
+        t->wt[i] = t->w[i];
+    }
+    double *wxx = t->wm[0], *wyy = t->wm[1], *wzz = t->wm[2];
+    double *wxy = t->wm[3], *wyz = t->wm[4], *wzx = t->wm[5];
+    wxx[1] = wxx[2] = 5.0 / 12.0;
+    wyy[3] = wyy[4] = 5.0 / 12.0;
+    wzz[5] = wzz[6] = 5.0 / 12.0;
+    for (int i = 3; i <= 6; i++) wxx[i] = -1.0 / 3.0;
+    wyy[1] = wyy[2] = wyy[5] = wyy[6] = -1.0 / 3.0;
+    for (int i = 1; i <= 4; i++) wzz[i] = -1.0 / 3.0;
+    for (int i = 7; i <= 10; i++) wxx[i] = -1.0 / 24.0;
+    for (int i = 15; i <= 18; i++) wxx[i] = -1.0 / 24.0;
+    for (int i = 7; i <= 14; i++) wyy[i] = -1.0 / 24.0;
+    for (int i = 11; i <= 18; i++) wzz[i] = -1.0 / 24.0;
+    for (int i = 11; i <= 14; i++) wxx[i] = 1.0 / 12.0;
+    for (int i = 15; i <= 18; i++) wyy[i] = 1.0 / 12.0;
+    for (int i = 7; i <= 10; i++) wzz[i] = 1.0 / 12.0;
+    wxy[7] = wxy[10] = 0.25;
+    wxy[8] = wxy[9] = -0.25;
+    wyz[11] = wyz[14] = 0.25;
+    wyz[12] = wyz[13] = -0.25;
+    wzx[15] = wzx[18] = 0.25;
+    wzx[16] = wzx[17] = -0.25;
+    double A = (1.0 - 8.0 * p->B) / 2.0;  /* 2A + 8B = 1 */
+    double C = 1.0 - 4.0 * p->D;          /* C + 4D = 1 */
+    double Ef = (1.0 - 8.0 * p->F) / 2.0;
+    build_gradient(3, A, p->B, t->gx, t->gy, t->gz);
+    build_laplacian(3, C, p->D, t->lap);
+    build_gradient(3, Ef, p->F, t->fx, t->fy, t->fz);
+}
+
+/* ---- lattice helpers ---------------------------------------------------- */
+
+static inline int wrap(int v, int n) { v %= n; return v < 0 ? v + n : v; }
+
+static inline long sidx(const orc_params *p, int x, int y, int z)
+{
+    return ((long)wrap(z, p->nz) * p->ny + wrap(y, p->ny)) * p->nx + wrap(x, p->nx);
+}
+
+static inline long nsites(const orc_params *p) { return (long)p->nx * p->ny * p->nz; }
+
+/* apply a 3x3x3 stencil (paper layout) to a scalar field at (x,y,z) */
+static double apply(const orc_params *p, const double s[3][3][3], const double *fld,
+                    int x, int y, int z)
+{
+    double acc = 0.0;
+    for (int sl = 0; sl < 3; sl++)
+        for (int r = 0; r < 3; r++)
+            for (int c = 0; c < 3; c++) {
+                double k = s[sl][r][c];
+                if (k == 0.0) continue;
+                acc += k * fld[sidx(p, x + c - 1, y + 1 - r, z + 1 - sl)];
+            }
+    return acc;
+}
+
+/* ---- thermodynamics: Eq. (p0) and c_s^2 = dp0/drho ------------------------ */
+
+double orc_p0(double a, double b, double T, double rho)
+{
+    return rho * T / (1.0 - b * rho) - a * rho * rho;
+}
+
+double orc_cs2(double a, double b, double T, double rho)
+{
+    double d = 1.0 - b * rho;
+    return T / (d * d) - 2.0 * a * rho;
+}
+
+/* ---- per-site equilibrium and forcing ------------------------------------- */
+
+/* Eq. (equilibrium) for i >= 1 and Eq. (feq0) for i = 0.
+ * grad = discrete gradient of rho, lap = discrete Laplacian of rho.
+ * with_m = 1 adds the kappa d_a rho d_b rho terms (equilibrium scheme). */
+static void feq_site_t(const orc_params *p, const tables *t, double rho, const double j[3],
+                       const double grad[3], double lap, int with_m, double *feq)
+{
+    int dim = t->dim;
+    double u[3] = {j[0] / rho, j[1] / rho, j[2] / rho};
+    double p0 = orc_p0(p->a, p->b, p->T, rho);
+    double nu = (p->tau - 0.5) / 3.0;                  /* Eq. (viscous) */
+    double lam = p->lambda_on ? nu * (1.0 - 3.0 * orc_cs2(p->a, p->b, p->T, rho)) : 0.0;
+    double udg = 0.0;
+    for (int g = 0; g < dim; g++) udg += u[g] * grad[g];
+    double X[3][3];
+    for (int al = 0; al < 3; al++)
+        for (int be = 0; be < 3; be++) {
+            X[al][be] = rho * u[al] * u[be] +
+                        lam * (u[al] * grad[be] + u[be] * grad[al] + (al == be ? udg : 0.0));
+        }
+    double M[6] = {p->kappa * grad[0] * grad[0], p->kappa * grad[1] * grad[1],
+                   p->kappa * grad[2] * grad[2], p->kappa * grad[0] * grad[1],
+                   p->kappa * grad[1] * grad[2], p->kappa * grad[2] * grad[0]};
+    double sum = 0.0;
+    for (int i = 1; i < t->q; i++) {
+        const int *e = t->e[i];
+        double ej = 0.0, ex = 0.0;
+        for (int al = 0; al < dim; al++) ej += e[al] * j[al];
+        for (int al = 0; al < dim; al++)
+            for (int be = 0; be < dim; be++)
+                ex += (e[al] * e[be] - (al == be ? 1.0 / 3.0 : 0.0)) * X[al][be];
+        double v = t->w[i] * (ej + 1.5 * ex) + t->wp[i] * p0 - t->wt[i] * p->kappa * rho * lap;
+        if (with_m)
+            for (int m = 0; m < 6; m++) v += t->wm[m][i] * M[m];
+        feq[i] = v;
+        sum += v;
+    }
+    feq[0] = rho - sum;
+}
+
+/* Forcing term of Section "Using a forcing method" for i >= 1; the rest
+ * term closes the zeroth moment. */
+static void force_site_t(const tables *t, const double u[3], const double g[3], double *F)
+{
+    int dim = t->dim;
+    double sum = 0.0;
+    for (int i = 1; i < t->q; i++) {
+        const int *e = t->e[i];
+        double eg = 0.0, ex = 0.0;
+        for (int al = 0; al < dim; al++) eg += e[al] * g[al];
+        for (int al = 0; al < dim; al++)
+            for (int be = 0; be < dim; be++)
+                ex += (e[al] * e[be] - (al == be ? 1.0 / 3.0 : 0.0)) *
+                      (u[al] * g[be] + u[be] * g[al]);
+        F[i] = t->w[i] * (eg + 1.5 * ex);
+        sum += F[i];
+    }
+    F[0] = -sum;
+}
+
+/* ---- fields ----------------------------------------------------------------- */
+
+/* Eq. (rho): rho = sum_i f_i, j = sum_i f_i e_i */
+static void moments(const orc_params *p, const tables *t, const double *f, double *rho,
+                    double *j)
+{
+    long n = nsites(p);
+#pragma omp parallel for schedule(static)
+    for (long s = 0; s < n; s++) {
+        double r = 0, jx = 0, jy = 0, jz = 0;
+        for (int i = 0; i < t->q; i++) {
+            double v = f[i * n + s];
+            r += v;
+            jx += v * t->e[i][0];
+            jy += v * t->e[i][1];
+            jz += v * t->e[i][2];
+        }
+        rho[s] = r;
+        j[s] = jx;
+        j[n + s] = jy;
+        j[2 * n + s] = jz;
+    }
+}
+
+static void stencil_field(const orc_params *p, const double s[3][3][3], const double *in,
+                          double *out)
+{
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int z = 0; z < p->nz; z++)
+        for (int y = 0; y < p->ny; y++)
+            for (int x = 0; x < p->nx; x++)
+                out[sidx(p, x, y, z)] = apply(p, s, in, x, y, z);
+}
+
+/* gradient (3 components, z zero in 2D) and Laplacian of rho */
+static void derivatives(const orc_params *p, const tables *t, const double *rho,
+                        double *grad, double *lap)
+{
+    long n = nsites(p);
+    stencil_field(p, t->gx, rho, grad);
+    stencil_field(p, t->gy, rho, grad + n);
+    if (t->dim == 3) stencil_field(p, t->gz, rho, grad + 2 * n);
+    else memset(grad + 2 * n, 0, sizeof(double) * n);
+    stencil_field(p, t->lap, rho, lap);
+}
+
+/* Body force of the forcing scheme: g_a = -d_b (M_ab - delta_ab M_gg / 2)
+ * with M_ab = kappa d_a rho d_b rho, derivatives taken with the force
+ * stencil.  In 2D this is g_x = -d_x((M_xx - M_yy)/2) - d_y M_xy as printed. */
+static void body_force(const orc_params *p, const tables *t, const double *grad, double *g)
+{
+    long n = nsites(p);
+    int dim = t->dim;
+    double *T = (double *)malloc(sizeof(double) * n * 9); /* T_ab = M_ab - delta tr/2 */
+    double *tmp = (double *)malloc(sizeof(double) * n);
+    for (long s = 0; s < n; s++) {
+        double d[3] = {grad[s], grad[n + s], grad[2 * n + s]};
+        double tr = 0.0;
+        for (int g2 = 0; g2 < dim; g2++) tr += p->kappa * d[g2] * d[g2];
+        for (int al = 0; al < 3; al++)
+            for (int be = 0; be < 3; be++)
+                T[(al * 3 + be) * n + s] =
+                    p->kappa * d[al] * d[be] - (al == be ? 0.5 * tr : 0.0);
+    }
+    const double(*fs[3])[3][3] = {t->fx, t->fy, t->fz};
+    for (int al = 0; al < 3; al++) {
+        for (long s = 0; s < n; s++) g[al * n + s] = 0.0;
+        if (al >= dim) continue;
+        for (int be = 0; be < dim; be++) {
+            stencil_field(p, fs[be], T + (al * 3 + be) * n, tmp);
+            for (long s = 0; s < n; s++) g[al * n + s] -= tmp[s];
+        }
+    }
+    free(T);
+    free(tmp);
+}
+
+/* ---- public entry points ------------------------------------------------------ */
+
+int orc_num_sites(const orc_params *p) { return (int)nsites(p); }
+
+/* Stencils as the 27 coefficients [slice][row][col] (for the Taylor tests). */
+void orc_stencils(const orc_params *p, double *gx, double *gy, double *gz, double *lap,
+                  double *fx, double *fy, double *fz)
+{
+    tables t;
+    build_tables(p, &t);
+    memcpy(gx, t.gx, sizeof(t.gx));
+    memcpy(gy, t.gy, sizeof(t.gy));
+    memcpy(gz, t.gz, sizeof(t.gz));
+    memcpy(lap, t.lap, sizeof(t.lap));
+    memcpy(fx, t.fx, sizeof(t.fx));
+    memcpy(fy, t.fy, sizeof(t.fy));
+    memcpy(fz, t.fz, sizeof(t.fz));
+}
+
+/* Velocity set and weight tables: e[q*3], w, wp, wt [q], wm[6*q]. */
+void orc_tables(const orc_params *p, int *e, double *w, double *wp, double *wt, double *wm)
+{
+    tables t;
+    build_tables(p, &t);
+    for (int i = 0; i < t.q; i++) {
+        for (int a = 0; a < 3; a++) e[i * 3 + a] = t.e[i][a];
+        w[i] = t.w[i];
+        wp[i] = t.wp[i];
+        wt[i] = t.wt[i];
+        for (int m = 0; m < 6; m++) wm[m * t.q + i] = t.wm[m][i];
+    }
+}
+
+/* Equilibrium at one site for given moments and derivatives. */
+void orc_feq_site(const orc_params *p, double rho, const double *j, const double *grad,
+                  double lap, double *feq)
+{
+    tables t;
+    build_tables(p, &t);
+    feq_site_t(p, &t, rho, j, grad, lap, p->scheme == 0, feq);
+}
+
+/* Forcing term at one site for given u and g. */
+void orc_force_site(const orc_params *p, const double *u, const double *g, double *F)
+{
+    tables t;
+    build_tables(p, &t);
+    force_site_t(&t, u, g, F);
+}
+
+/* Discrete gradient [3][n] and Laplacian [n] of a scalar field. */
+void orc_derivatives(const orc_params *p, const double *rho, double *grad, double *lap)
+{
+    tables t;
+    build_tables(p, &t);
+    derivatives(p, &t, rho, grad, lap);
+}
+
+/* Body force [3][n] of the forcing scheme for a density field. */
+void orc_body_force(const orc_params *p, const double *rho, double *g)
+{
+    tables t;
+    build_tables(p, &t);
+    long n = nsites(p);
+    double *grad = (double *)malloc(sizeof(double) * 3 * n);
+    double *lap = (double *)malloc(sizeof(double) * n);
+    derivatives(p, &t, rho, grad, lap);
+    body_force(p, &t, grad, g);
+    free(grad);
+    free(lap);
+}
+
+/* Initial populations f_i = f_i^eq(rho0, rho0 u0) of the active scheme
+ * (u0 may be NULL for a fluid at rest). */
+void orc_init(const orc_params *p, const double *rho0, const double *u0, double *f)
+{
+    tables t;
+    build_tables(p, &t);
+    long n = nsites(p);
+    double *grad = (double *)malloc(sizeof(double) * 3 * n);
+    double *lap = (double *)malloc(sizeof(double) * n);
+    derivatives(p, &t, rho0, grad, lap);
+#pragma omp parallel for schedule(static)
+    for (long s = 0; s < n; s++) {
+        double j[3] = {0, 0, 0};
+        if (u0)
+            for (int a = 0; a < 3; a++) j[a] = rho0[s] * u0[a * n + s];
+        double g[3] = {grad[s], grad[n + s], grad[2 * n + s]};
+        double feq[19];
+        feq_site_t(p, &t, rho0[s], j, g, lap[s], p->scheme == 0, feq);
+        for (int i = 0; i < t.q; i++) f[i * n + s] = feq[i];
+    }
+    free(grad);
+    free(lap);
+}
+
+/* One time step, Eq. (latbolt): f_out(r + e_i) = f_i - (f_i - f_i^eq)/tau + F_i. */
+static void step_t(const orc_params *p, const tables *t, const double *f, double *fout,
+                   double *rho, double *j, double *grad, double *lap, double *g)
+{
+    long n = nsites(p);
+    int force = (p->scheme == 1);
+    moments(p, t, f, rho, j);
+    derivatives(p, t, rho, grad, lap);
+    if (force) body_force(p, t, grad, g);
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int z = 0; z < p->nz; z++)
+        for (int y = 0; y < p->ny; y++)
+            for (int x = 0; x < p->nx; x++) {
+                long s = sidx(p, x, y, z);
+                double jj[3] = {j[s], j[n + s], j[2 * n + s]};
+                double gr[3] = {grad[s], grad[n + s], grad[2 * n + s]};
+                double feq[19], F[19];
+                feq_site_t(p, t, rho[s], jj, gr, lap[s], !force, feq);
+                if (force) {
+                    double u[3] = {jj[0] / rho[s], jj[1] / rho[s], jj[2] / rho[s]};
+                    double gg[3] = {g[s], g[n + s], g[2 * n + s]};
+                    force_site_t(t, u, gg, F);
+                } else {
+                    for (int i = 0; i < t->q; i++) F[i] = 0.0;
+                }
+                for (int i = 0; i < t->q; i++) {
+                    double fi = f[i * n + s];
+                    double fstar = fi - (fi - feq[i]) / p->tau + F[i];
+                    const int *e = t->e[i];
+                    fout[i * n + sidx(p, x + e[0], y + e[1], z + e[2])] = fstar;
+                }
+            }
+}
+
+/* Advance f (in place) by nsteps. Returns 0, or -1 on a bad argument. */
+int orc_run(const orc_params *p, double *f, int nsteps)
+{
+    if (!(p->q == 9 || p->q == 19) || nsteps < 0) return -1;
+    if (p->q == 9 && p->nz != 1) return -1;
+    tables t;
+    build_tables(p, &t);
+    long n = nsites(p);
+    double *buf = (double *)malloc(sizeof(double) * n * t.q);
+    double *rho = (double *)malloc(sizeof(double) * n);
+    double *j = (double *)malloc(sizeof(double) * 3 * n);
+    double *grad = (double *)malloc(sizeof(double) * 3 * n);
+    double *lap = (double *)malloc(sizeof(double) * n);
+    double *g = (double *)malloc(sizeof(double) * 3 * n);
+    double *cur = f, *nxt = buf;
+    for (int s = 0; s < nsteps; s++) {
+        step_t(p, &t, cur, nxt, rho, j, grad, lap, g);
+        double *tmp = cur; cur = nxt; nxt = tmp;
+    }
+    if (cur != f) memcpy(f, cur, sizeof(double) * n * t.q);
+    free(buf); free(rho); free(j); free(grad); free(lap); free(g);
+    return 0;
+}
+
+/* Observables: rho [n] and the velocity [3][n]: u = j/rho for the
+ * equilibrium scheme, v = u + g/(2 rho) for the forcing scheme. */
+void orc_observe(const orc_params *p, const double *f, double *rho, double *vel)
+{
+    tables t;
+    build_tables(p, &t);
+    long n = nsites(p);
+    double *j = (double *)malloc(sizeof(double) * 3 * n);
+    moments(p, &t, f, rho, j);
+    for (long s = 0; s < n; s++)
+        for (int a = 0; a < 3; a++) vel[a * n + s] = j[a * n + s] / rho[s];
+    if (p->scheme == 1) {
+        double *g = (double *)malloc(sizeof(double) * 3 * n);
+        double *grad = (double *)malloc(sizeof(double) * 3 * n);
+        double *lap = (double *)malloc(sizeof(double) * n);
+        derivatives(p, &t, rho, grad, lap);
+        body_force(p, &t, grad, g);
+        for (long s = 0; s < n; s++)
+            for (int a = 0; a < 3; a++) vel[a * n + s] += g[a * n + s] / (2.0 * rho[s]);
+        free(g); free(grad); free(lap);
+    }
+    free(j);
+}
+
+/* ---- site-local evaluation (for sampled checks on large lattices) ---------- */
+
+static double rho_at(const orc_params *p, const tables *t, const double *f, int x, int y, int z)
+{
+    long n = nsites(p), s = sidx(p, x, y, z);
+    double r = 0.0;
+    for (int i = 0; i < t->q; i++) r += f[i * n + s];
+    return r;
+}
+
+static double apply_rho(const orc_params *p, const tables *t, const double s[3][3][3],
+                        const double *f, int x, int y, int z)
+{
+    double acc = 0.0;
+    for (int sl = 0; sl < 3; sl++)
+        for (int r = 0; r < 3; r++)
+            for (int c = 0; c < 3; c++) {
+                double k = s[sl][r][c];
+                if (k == 0.0) continue;
+                acc += k * rho_at(p, t, f, x + c - 1, y + 1 - r, z + 1 - sl);
+            }
+    return acc;
+}
+
+static void grad_at(const orc_params *p, const tables *t, const double *f, int x, int y,
+                    int z, double d[3])
+{
+    d[0] = apply_rho(p, t, t->gx, f, x, y, z);
+    d[1] = apply_rho(p, t, t->gy, f, x, y, z);
+    d[2] = (t->dim == 3) ? apply_rho(p, t, t->gz, f, x, y, z) : 0.0;
+}
+
+/* Post-collision populations f*_i(r) (before streaming) at a list of sites
+ * given as (x,y,z) triples; out is [nsite][q].  The post-stream state
+ * after the step has f_i(r + e_i) = f*_i(r). */
+void orc_collide_sites(const orc_params *p, const double *f, int nsite, const int *xyz,
+                       double *out)
+{
+    tables t;
+    build_tables(p, &t);
+    long n = nsites(p);
+    int force = (p->scheme == 1);
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int k = 0; k < nsite; k++) {
+        int x = xyz[3 * k], y = xyz[3 * k + 1], z = xyz[3 * k + 2];
+        long s = sidx(p, x, y, z);
+        double rho = 0, j[3] = {0, 0, 0};
+        for (int i = 0; i < t.q; i++) {
+            double v = f[i * n + s];
+            rho += v;
+            for (int a = 0; a < 3; a++) j[a] += v * t.e[i][a];
+        }
+        double d[3];
+        grad_at(p, &t, f, x, y, z, d);
+        double lap = apply_rho(p, &t, t.lap, f, x, y, z);
+        double feq[19], F[19] = {0};
+        feq_site_t(p, &t, rho, j, d, lap, !force, feq);
+        if (force) {
+            /* g_a = -sum_b sum_stencil k * T_ab(neighbour) */
+            const double(*fs[3])[3][3] = {t.fx, t.fy, t.fz};
+            double g[3] = {0, 0, 0};
+            for (int sl = 0; sl < 3; sl++)
+                for (int r = 0; r < 3; r++)
+                    for (int c = 0; c < 3; c++) {
+                        int nbx = x + c - 1, nby = y + 1 - r, nbz = z + 1 - sl;
+                        int any = 0;
+                        for (int be = 0; be < t.dim; be++) any |= (fs[be][sl][r][c] != 0.0);
+                        if (!any) continue;
+                        double dn[3];
+                        grad_at(p, &t, f, nbx, nby, nbz, dn);
+                        double tr = 0.0;
+                        for (int g2 = 0; g2 < t.dim; g2++) tr += p->kappa * dn[g2] * dn[g2];
+                        for (int al = 0; al < t.dim; al++)
+                            for (int be = 0; be < t.dim; be++) {
+                                double Tab = p->kappa * dn[al] * dn[be] -
+                                             (al == be ? 0.5 * tr : 0.0);
+                                g[al] -= fs[be][sl][r][c] * Tab;
+                            }
+                    }
+            double u[3] = {j[0] / rho, j[1] / rho, j[2] / rho};
+            force_site_t(&t, u, g, F);
+        }
+        for (int i = 0; i < t.q; i++) {
+            double fi = f[i * n + s];
+            out[(long)k * t.q + i] = fi - (fi - feq[i]) / p->tau + F[i];
+        }
+    }
+}
+
+/* Totals: mass = sum rho, momentum = sum_r sum_i f_i e_i (FP64, serial). */
+void orc_totals(const orc_params *p, const double *f, double *mass, double *mom)
+{
+    tables t;
+    build_tables(p, &t);
+    long n = nsites(p);
+    double m = 0, mx = 0, my = 0, mz = 0;
+    for (int i = 0; i < t.q; i++)
+        for (long s = 0; s < n; s++) {
+            double v = f[i * n + s];
+            m += v;
+            mx += v * t.e[i][0];
+            my += v * t.e[i][1];
+            mz += v * t.e[i][2];
+        }
+    *mass = m;
+    mom[0] = mx;
+    mom[1] = my;
+    mom[2] = mz;
+}
