@@ -1,0 +1,206 @@
+"""Benchmark of the fused free-energy LBM step on one MI355X.
+
+Default workload: D3Q19 256^3 periodic lattice, FP32 shifted populations with
+FP64 reductions, momentum-conserving forcing scheme, one spherical drop R = 48
+plus 0.01-amplitude seeded uniform density noise, kappa = 0.02, tau = 0.8,
+a = 9/49, b = 2/21 and T = 0.56 (the paper's temperature: at T = 0.5 the
+coexisting liquid is linearly unstable in this scheme for kappa = 0.02).
+A step is one launch of the fused kernel over the whole lattice.
+
+Prints ONE JSON line: MLUPS (whole job), the dominant kernel's roofline
+(algorithmic bytes = 19 populations read + written = 152 B per site for
+FP32, over the average launch time from HIP events on the launch stream),
+and the FP64 CPU oracle timed on the host cores on a bounded sample.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0  # MI355X HBM3E datasheet peak
+A_VDW, B_VDW = 9.0 / 49.0, 2.0 / 21.0
+WORKLOADS = {
+    # name: (lattice, scheme, storage, compute, shape, T, kappa, tau, radius, noise)
+    "d3q19_256_fp32_force": (19, 1, 1, 0, (256, 256, 256), 0.56, 0.02, 0.8, 48.0, 0.01),
+    "d3q19_256_fp32s_f64math_force": (19, 1, 1, 1, (256, 256, 256), 0.56, 0.02, 0.8, 48.0, 0.01),
+    "d3q19_256_fp64_force": (19, 1, 0, 0, (256, 256, 256), 0.56, 0.02, 0.8, 48.0, 0.01),
+    "d3q19_256_fp32_eq": (19, 0, 1, 0, (256, 256, 256), 0.56, 0.02, 0.8, 48.0, 0.01),
+    "d2q9_1024_fp64_eq": (9, 0, 0, 0, (1024, 1024), 0.56, 0.01, 1.0, 28.0, 0.0),
+    "d2q9_1024_fp32_force": (9, 1, 1, 0, (1024, 1024), 0.56, 0.01, 1.0, 28.0, 0.0),
+}
+KERNEL_SOURCES = ["paper_0710_5470_amd/csrc/lbm_step.h", "paper_0710_5470_amd/csrc/lbm_lattice.h"]
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload):
+    """HBM bytes per launch from the committed rocprofv3 --pmc summary, if it
+    was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "step_kernel_%s_pmc.json" % workload)
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    if d.get("kernel_source_sha") != kernel_hash():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(wl):
+    """Time the FP64 CPU oracle on a bounded sample of the same workload: a
+    256 x 256 x 48 periodic slab (D3Q19) or a 1024 x 1024 box (D2Q9) with
+    the same parameters, 6 steps, all host threads OpenMP allows."""
+    import numpy as np
+    import oracle
+    from paper_0710_5470_amd import inputs
+    q, scheme, _, _, shape, T, kappa, tau, R, noise = WORKLOADS[wl]
+    from oracle import thermo
+    g, l, _ = thermo.coexistence(A_VDW, B_VDW, T)
+    sample = (256, 256, 48) if q == 19 else (1024, 1024)
+    rho = inputs.tanh_drop(sample, min(R, min(sample) / 3), l, g, 2.0)
+    if noise:
+        rho = rho + inputs.uniform_noise(sample, noise, 3)
+    p = oracle.params(q=q, scheme=scheme, shape=sample, T=T, kappa=kappa, tau=tau)
+    f = oracle.init(p, rho)
+    steps = 6
+    t0 = time.perf_counter()
+    f = oracle.run(p, f, steps)
+    dt = time.perf_counter() - t0
+    sites = int(np.prod(sample))
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": sites * steps / dt / 1e6, "unit": "MLUPS", "cores": cores, "kind": "oracle",
+            "sample": "%s periodic lattice, same physics, %d steps, FP64 C oracle (%.2f s)"
+                      % ("x".join(map(str, sample)), steps, dt)}
+
+
+def copy_calibration(nbytes, reps):
+    """A plain device-to-device copy of nbytes (read nbytes, write nbytes),
+    repeated; its FETCH_SIZE / WRITE_SIZE counters scale the LBM kernel's."""
+    import torch
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    print(json.dumps({"copy_bytes": a.numel() * 4, "reps": reps, "ms": ms,
+                      "GBps_read_plus_write": 2 * a.numel() * 4 / (ms * 1e-3) / 1e9}), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--warmup", type=int, default=40)
+    ap.add_argument("--workload", default="d3q19_256_fp32_force", choices=sorted(WORKLOADS))
+    ap.add_argument("--tile", type=int, default=-1)
+    ap.add_argument("--planes", type=int, default=0)
+    ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="instead: time a plain device copy of this many bytes (HBM counter "
+                         "calibration for rocprofv3 --pmc)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if args.copy_bytes:
+        return copy_calibration(args.copy_bytes, args.steps)
+    from paper_0710_5470_amd import autotune, inputs, lbm
+
+    wl = args.workload
+    q, scheme, storage, compute, shape, T, kappa, tau, R, noise = WORKLOADS[wl]
+    g, l = lbm.lbm_coexistence(A_VDW, B_VDW, T)
+    if q == 19:
+        rho0 = inputs.sphere_with_noise(shape[0], R, g, l, noise, 3)
+    else:
+        rho0, _, _ = inputs.multi_drop(shape, 64, 8.0, 48.0, g, l, seed=2)
+    p = lbm.params(lattice=q, scheme=scheme, storage=storage, shape=shape, T=T, kappa=kappa,
+                   tau=tau, compute=compute)
+    sim = lbm.Simulation(p, rho0)
+    n = sim.n
+    tune = None
+    if args.tile >= 0 or args.planes > 0:
+        sim.set_launch(args.tile, args.planes)
+    elif not args.no_tune:
+        tune = autotune.autotune(sim, use_cache=False, verbose=True)
+    tile, planes, wgs = sim.launch()
+    sim.step(args.warmup)
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    sim.step(args.steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kern_ms = e0.elapsed_time(e1) / args.steps
+    mass, mom = sim.invariants()
+    ok = True
+    try:
+        vmax = sim.max_spurious_u()
+    except lbm.LBMError:
+        vmax, ok = float("nan"), False
+
+    bytes_site = q * 2 * (8 if storage == 0 else 4)
+    mlups = n * args.steps / wall / 1e6
+    achieved = bytes_site * n / (kern_ms * 1e-3) / 1e9
+    traffic = measured_traffic(wl)
+    out = {
+        "metric": "MLUPS (D3Q19 FP32 256^3 fused free-energy LBM step)",
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall * 1e3 / args.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if (storage == 1 and compute == 0) else "f64",
+        "data": "synthetic",
+        "config": {"workload": wl, "lattice": "D3Q19" if q == 19 else "D2Q9",
+                   "extent": list(shape), "scheme": "force" if scheme else "equilibrium",
+                   "storage": "fp32_shifted" if storage else "fp64",
+                   "T": T, "kappa": kappa, "tau": tau, "a": A_VDW, "b": B_VDW,
+                   "init": "drop R=%g + noise %g (seed 3)" % (R, noise) if q == 19
+                   else "64 drops R in [8,48] (seed 2)",
+                   "launch": {"tile": lbm.lbm_tile_shape(q, tile), "planes_per_workgroup": planes,
+                              "workgroups": wgs, "autotuned": tune is not None}},
+        "hbm_gbs_algorithmic": round(achieved, 1),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
+                     "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
+                     "traffic": traffic, "bytes_per_site": bytes_site,
+                     "kernel_ms": round(kern_ms, 5)},
+        "state_after": {"finite": ok, "max_vel": vmax, "mass": mass, "momentum": mom},
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(wl)
+    sim.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,192 @@
+/*
+ * lbm.h -- C ABI of the MI355X (gfx950) free-energy lattice Boltzmann library.
+ *
+ * The library advances the liquid-gas free-energy lattice Boltzmann model of
+ * Pooley & Furtado, "Eliminating spurious velocities in the free energy
+ * lattice Boltzmann method", on periodic D2Q9 and D3Q19 lattices:
+ *   - density and momentum moments                 Section "Model", Eq. (rho)
+ *   - isotropic gradient / Laplacian stencils      Eqs. (xderiv), (laplace), (best),
+ *                                                  3D: Eq. (laplacian3d)
+ *   - van der Waals bulk pressure                  Eq. (p0)
+ *   - tuned equilibrium (scheme LBM_SCHEME_EQ)     Eq. (equilibrium), Eq. (feq0),
+ *                                                  2D weights: Section "Summary",
+ *                                                  3D weights: Eq. (3dres)
+ *   - momentum-conserving body force               Section "Using a forcing method"
+ *     (scheme LBM_SCHEME_FORCE, 2-site halo)
+ *   - BGK collision and streaming                  Eq. (latbolt)
+ *   - the lambda (Galilean invariance) terms       Eq. (viscous), Appendix A
+ * Units are lattice units: dx = dt = c = 1.
+ *
+ * Conventions shared by every entry point
+ *   - Every pointer named dev_* is a device pointer on the current HIP device;
+ *     host_* pointers are host memory.  The caller owns every buffer.  The
+ *     library allocates no device memory: all device scratch lives in the
+ *     caller's workspace (lbm_workspace_bytes / lbm_init).
+ *   - Fields are FP64, SoA, x fastest: a scalar field is [nz][ny][nx]
+ *     (nz = 1 for D2Q9), a vector field is [3][nz][ny][nx] (the z component
+ *     of a D2Q9 vector field is written as zero), populations are
+ *     [q][nz][ny][nx] in the paper's numbering of the velocities (D2Q9:
+ *     e1,2 = (+-1,0), e3,4 = (0,+-1), e5,6 = (+-1,+-1), e7,8 = (-+1,+-1);
+ *     D3Q19: faces e1..e6 then e7..e18 as printed in Section "Extension to
+ *     3D").  Populations exchanged through the ABI are the paper's f_i(r,t),
+ *     the values at site r after streaming.
+ *   - All work is enqueued on the HIP stream given to lbm_init (NULL = the
+ *     default stream).  Entry points that return host values synchronise
+ *     that stream; the others only enqueue work.
+ *   - Every function returns an int status: LBM_OK (0) or a negative
+ *     LBM_E_* code; lbm_strerror() names it.  No C++ exception crosses the
+ *     ABI.  A failed call leaves the context usable unless it returned
+ *     LBM_E_DEVICE.
+ *   - A context is not thread-safe; calls on one context must not overlap.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm_ctx lbm_ctx;
+
+enum { LBM_D2Q9 = 9, LBM_D3Q19 = 19 };
+enum { LBM_SCHEME_EQ = 0, LBM_SCHEME_FORCE = 1 };
+/* FP64 populations, or FP32 deviations delta_i = f_i - s_i from a fixed
+ * per-direction shift s_i (arithmetic in FP32, reductions in FP64). */
+enum { LBM_STORE_F64 = 0, LBM_STORE_F32_SHIFTED = 1 };
+/* Shift of the FP32 storage: the rest equilibrium at rho_shift
+ * (s_i = f_i^eq(rho_shift, u = 0)), or the normalised lattice weights times
+ * rho_shift (2D 4/9, 1/9, 1/36; 3D 1/3, 1/18, 1/36). */
+enum { LBM_SHIFT_REST_EQ = 0, LBM_SHIFT_WEIGHTS = 1 };
+/* Arithmetic of the step kernels: the storage precision (FP64 storage ->
+ * FP64, FP32 storage -> FP32), or FP64 arithmetic on FP32-stored deviations. */
+enum { LBM_COMPUTE_NATIVE = 0, LBM_COMPUTE_F64 = 1 };
+
+enum {
+    LBM_OK = 0,
+    LBM_E_INVAL = -1,     /* bad argument or unphysical parameter          */
+    LBM_E_NOMEM = -2,     /* workspace smaller than lbm_workspace_bytes()  */
+    LBM_E_DEVICE = -3,    /* a HIP call or kernel launch failed            */
+    LBM_E_NONFINITE = -4, /* non-finite value or b*rho >= 1 in the state   */
+    LBM_E_STATE = -5      /* call not valid in the context's current state */
+};
+
+typedef struct {
+    double a, b, T;       /* van der Waals constants and temperature, Eq. (p0)  */
+    double kappa;         /* square-gradient coefficient, Eq. (pt)              */
+    double tau;           /* BGK relaxation time, Eq. (latbolt); > 1/2          */
+    int lattice;          /* LBM_D2Q9 or LBM_D3Q19                              */
+    int scheme;           /* LBM_SCHEME_EQ or LBM_SCHEME_FORCE                  */
+    int storage;          /* LBM_STORE_F64 or LBM_STORE_F32_SHIFTED             */
+    int nx, ny, nz;       /* lattice extent; nz = 1 for D2Q9                    */
+    /* Stencil and weight overrides for parameter scans; NaN = the paper's
+     * optimum.  B: gradient off-axis coefficient (Eq. (xderiv), 2A + 4B = 1
+     * in 2D, 2A + 8B = 1 in 3D); D: Laplacian off-axis coefficient
+     * (Eq. (laplace), C + 2D = 1 in 2D, C + 4D = 1 in 3D); F: force stencil
+     * off-axis coefficient.  wp_diag, wt_diag, wxx_diag: the D2Q9
+     * equilibrium weights w^p_5-8, w^t_5-8, w^xx_5-8 (the axis weights follow
+     * from the constraints after Eq. (fi)); must be NaN for D3Q19. */
+    double B, D, F;
+    double wp_diag, wt_diag, wxx_diag;
+    int galilean_lambda;  /* 1 = include the lambda terms (default), 0 = drop */
+    int shift_mode;       /* LBM_SHIFT_REST_EQ or LBM_SHIFT_WEIGHTS            */
+    double rho_shift;     /* FP32 shift density; NaN = mean of the initial rho */
+    int tile;             /* launch shape id (lbm_tile_count); -1 = default     */
+    int planes_per_block; /* planes marched by one workgroup; <= 0 = default    */
+    int compute;          /* LBM_COMPUTE_NATIVE or LBM_COMPUTE_F64              */
+} lbm_params;
+
+/* Fill *p with the paper's drop-experiment defaults (a = 9/49, b = 2/21,
+ * T = 0.56, kappa = 0.025, tau = 1, D2Q9, equilibrium scheme, FP64, 100x100,
+ * every override NaN, lambda terms on, tile -1, native arithmetic). */
+void lbm_params_default(lbm_params *p);
+
+/* Bytes of device workspace lbm_init needs for these parameters (0 if the
+ * parameters are invalid).  The workspace holds two population buffers, the
+ * observation fields and the reduction partials. */
+size_t lbm_workspace_bytes(const lbm_params *p);
+
+/* Create a context and set the populations to the equilibrium of the
+ * active scheme for density dev_rho0 [n] and velocity dev_u0 [3][n]
+ * (dev_u0 may be NULL: fluid at rest).  The equilibrium includes the
+ * gradient terms of Eq. (equilibrium) evaluated with the stencils.
+ * dev_workspace must stay valid, and untouched by the caller, until
+ * lbm_destroy.  stream is a hipStream_t (NULL = default stream).
+ * Returns LBM_E_INVAL for bad parameters or an initial density that is
+ * non-finite, <= 0 or >= 1/b somewhere; LBM_E_NOMEM if bytes is too small.
+ * Synchronises the stream. */
+int lbm_init(lbm_ctx **out, const lbm_params *p, void *dev_workspace, size_t bytes,
+             void *stream, const double *dev_rho0, const double *dev_u0);
+
+/* Advance the state by nsteps >= 0 time steps, Eq. (latbolt).  Only
+ * enqueues work. */
+int lbm_step(lbm_ctx *ctx, long long nsteps);
+
+/* Density [n] and velocity [3][n] of the current state: u = j / rho for the
+ * equilibrium scheme, v = u + g / (2 rho) for the forcing scheme (end of
+ * Appendix A).  Either pointer may be NULL.  Only enqueues work. */
+int lbm_moments(lbm_ctx *ctx, double *dev_rho, double *dev_vel);
+
+/* Spurious velocity: the maximum velocity magnitude in the system (Section
+ * "Numerical results"), |u| or |v| as in lbm_moments, reduced in FP64.
+ * Returns LBM_E_NONFINITE if the state holds a non-finite value or
+ * b*rho >= 1.  Synchronises. */
+int lbm_max_spurious_u(lbm_ctx *ctx, double *host_out);
+
+/* FP64 totals of the current state: mass sum_r rho and momentum
+ * sum_r sum_i f_i e_i (host_mom[3]).  Synchronises. */
+int lbm_invariants(lbm_ctx *ctx, double *host_mass, double *host_mom);
+
+/* Advance nsteps >= 1 steps and report, for the last step t -> t+1, the
+ * steady-state residual max_r |vel(r,t+1) - vel(r,t)| and max_r |vel(r,t+1)|
+ * (FP64).  Either host pointer may be NULL.  Returns LBM_E_NONFINITE (after
+ * advancing) if the new state is non-finite or has b*rho >= 1.
+ * Synchronises. */
+int lbm_step_observed(lbm_ctx *ctx, long long nsteps, double *host_residual,
+                      double *host_max_vel);
+
+/* Copy the state out as FP64 post-streaming populations f_i(r,t) [q][n]
+ * (FP32 storage is decoded, shift added).  Only enqueues work. */
+int lbm_get_state(lbm_ctx *ctx, double *dev_f);
+
+/* Replace the state with FP64 post-streaming populations f_i(r,t) [q][n]
+ * (rounded to FP32 deviations for FP32 storage).  Only enqueues work. */
+int lbm_set_state(lbm_ctx *ctx, const double *dev_f);
+
+/* Number of time steps taken since lbm_init (lbm_set_state keeps it). */
+long long lbm_steps_done(const lbm_ctx *ctx);
+
+/* The per-direction FP32 shift s_i actually in use (host_shift[q]); zeros
+ * for FP64 storage. */
+int lbm_shift(const lbm_ctx *ctx, double *host_shift);
+
+/* Launch shapes: lbm_tile_count(lattice) shapes exist per lattice; shape k
+ * covers tile_x x tile_y sites of a plane per workgroup (tile_y = 1 for
+ * D2Q9, which marches along y; D3Q19 marches along z). */
+int lbm_tile_count(int lattice);
+int lbm_tile_shape(int lattice, int k, int *tile_x, int *tile_y);
+
+/* Select the launch shape and planes per workgroup for later steps
+ * (tile < 0 or planes <= 0 keep the current value).  Results do not depend
+ * on the shape. */
+int lbm_set_launch(lbm_ctx *ctx, int tile, int planes_per_block);
+int lbm_get_launch(const lbm_ctx *ctx, int *tile, int *planes_per_block, int *workgroups);
+
+/* Free the context (host memory only; the workspace stays the caller's). */
+int lbm_destroy(lbm_ctx *ctx);
+
+/* Coexisting gas and liquid densities of the van der Waals fluid of
+ * Eq. (p0) at temperature T < T_c = 8a/(27b): equal pressure and equal
+ * chemical potential mu = T ln(rho/(1-b rho)) + T/(1-b rho) - 2 a rho
+ * (Maxwell construction).  Host computation.  LBM_E_INVAL if T >= T_c. */
+int lbm_coexistence(double a, double b, double T, double *rho_gas, double *rho_liq);
+
+/* Human-readable name of a status code. */
+const char *lbm_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H */

@@ -1,0 +1,84 @@
+"""Launch-shape autotuner for the fused step kernel.
+
+Times every (tile shape, planes per workgroup) candidate on the live
+context with HIP events on the context's stream and keeps the fastest.
+Results never depend on the launch shape (every shape runs the same
+per-site arithmetic), so tuning only changes speed.  The best choice per
+(lattice, scheme, storage, compute, extent, device) is cached in a JSON file.
+"""
+import json
+import sys
+import os
+
+import torch
+
+from . import lbm
+
+CACHE = os.environ.get("LBM_TUNE_CACHE",
+                       os.path.join(os.path.expanduser("~"), ".cache", "lbm_mi355x_tune.json"))
+
+
+def _key(p):
+    dev = torch.cuda.get_device_name() if torch.cuda.is_available() else "none"
+    return "%s|q%d|s%d|st%d|c%d|%dx%dx%d" % (dev, p.lattice, p.scheme, p.storage, p.compute,
+                                            p.nx, p.ny, p.nz)
+
+
+def candidates(p):
+    np_ = p.nz if p.lattice == lbm.D3Q19 else p.ny
+    planes = sorted(set(min(c, np_) for c in (8, 16, 32, 64)))
+    return [(t, c) for t in range(lbm.lbm_tile_count(p.lattice)) for c in planes]
+
+
+def time_launch(sim, tile, planes, steps=10, reps=2):
+    """Average milliseconds per step for one launch shape."""
+    sim.set_launch(tile, planes)
+    stream = torch.cuda.current_stream()
+    sim.step(2)
+    best = float("inf")
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        sim.step(steps)
+        e1.record(stream)
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1) / steps)
+    return best
+
+
+def autotune(sim, steps=10, use_cache=True, verbose=False):
+    """Pick the fastest launch shape for `sim` and apply it.  The state
+    advances by the timing steps; callers that need a fixed state should
+    save it first (Simulation.get_state / set_state)."""
+    key = _key(sim.p)
+    cache = {}
+    if use_cache and os.path.exists(CACHE):
+        try:
+            with open(CACHE) as fh:
+                cache = json.load(fh)
+        except (OSError, ValueError):
+            cache = {}
+    if use_cache and key in cache:
+        t, c = cache[key]["tile"], cache[key]["planes"]
+        sim.set_launch(t, c)
+        return dict(cache[key], cached=True)
+    results = []
+    for t, c in candidates(sim.p):
+        ms = time_launch(sim, t, c, steps)
+        results.append((ms, t, c))
+        if verbose:
+            print("autotune tile %d planes %d: %.4f ms/step" % (t, c, ms), file=sys.stderr,
+                  flush=True)
+    ms, t, c = min(results)
+    sim.set_launch(t, c)
+    best = dict(tile=t, planes=c, ms=ms, tile_shape=lbm.lbm_tile_shape(sim.p.lattice, t))
+    if use_cache:
+        cache[key] = best
+        try:
+            os.makedirs(os.path.dirname(CACHE), exist_ok=True)
+            with open(CACHE, "w") as fh:
+                json.dump(cache, fh, indent=1)
+        except OSError:
+            pass
+    return dict(best, cached=False, table=[(t_, c_, m_) for m_, t_, c_ in results])

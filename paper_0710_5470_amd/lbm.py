@@ -1,0 +1,299 @@
+"""Thin Python binding of the C ABI in include/lbm.h (argument marshalling only).
+
+Every function here has the name of the C entry point it calls.  Device
+buffers are torch CUDA (HIP) tensors; the library computes everything in its
+own HIP kernels and never falls back to the CPU: if the shared library is
+missing, importing this module raises.
+
+`Simulation` is a small convenience owner of one context and its workspace.
+"""
+import ctypes
+import math
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "liblbm.so")
+
+D2Q9, D3Q19 = 9, 19
+SCHEME_EQ, SCHEME_FORCE = 0, 1
+STORE_F64, STORE_F32_SHIFTED = 0, 1
+SHIFT_REST_EQ, SHIFT_WEIGHTS = 0, 1
+COMPUTE_NATIVE, COMPUTE_F64 = 0, 1
+OK, E_INVAL, E_NOMEM, E_DEVICE, E_NONFINITE, E_STATE = 0, -1, -2, -3, -4, -5
+
+
+class lbm_params(ctypes.Structure):
+    _fields_ = [
+        ("a", ctypes.c_double), ("b", ctypes.c_double), ("T", ctypes.c_double),
+        ("kappa", ctypes.c_double), ("tau", ctypes.c_double),
+        ("lattice", ctypes.c_int), ("scheme", ctypes.c_int), ("storage", ctypes.c_int),
+        ("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
+        ("B", ctypes.c_double), ("D", ctypes.c_double), ("F", ctypes.c_double),
+        ("wp_diag", ctypes.c_double), ("wt_diag", ctypes.c_double), ("wxx_diag", ctypes.c_double),
+        ("galilean_lambda", ctypes.c_int), ("shift_mode", ctypes.c_int),
+        ("rho_shift", ctypes.c_double),
+        ("tile", ctypes.c_int), ("planes_per_block", ctypes.c_int),
+        ("compute", ctypes.c_int),
+    ]
+
+
+class LBMError(RuntimeError):
+    def __init__(self, code, where):
+        self.code = code
+        super().__init__("%s failed: %s (%d)" % (where, lbm_strerror(code), code))
+
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        "liblbm.so is not built (%s); run __graft_entry__.build() or "
+        "python paper_0710_5470_amd/build.py" % LIB_PATH)
+
+_L = ctypes.CDLL(LIB_PATH)
+_vp, _dp, _ip = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)
+_pp = ctypes.POINTER(lbm_params)
+_sig = {
+    "lbm_params_default": (None, [_pp]),
+    "lbm_workspace_bytes": (ctypes.c_size_t, [_pp]),
+    "lbm_init": (ctypes.c_int, [ctypes.POINTER(_vp), _pp, _vp, ctypes.c_size_t, _vp, _vp, _vp]),
+    "lbm_step": (ctypes.c_int, [_vp, ctypes.c_longlong]),
+    "lbm_moments": (ctypes.c_int, [_vp, _vp, _vp]),
+    "lbm_max_spurious_u": (ctypes.c_int, [_vp, _dp]),
+    "lbm_invariants": (ctypes.c_int, [_vp, _dp, _dp]),
+    "lbm_step_observed": (ctypes.c_int, [_vp, ctypes.c_longlong, _dp, _dp]),
+    "lbm_get_state": (ctypes.c_int, [_vp, _vp]),
+    "lbm_set_state": (ctypes.c_int, [_vp, _vp]),
+    "lbm_steps_done": (ctypes.c_longlong, [_vp]),
+    "lbm_shift": (ctypes.c_int, [_vp, _dp]),
+    "lbm_tile_count": (ctypes.c_int, [ctypes.c_int]),
+    "lbm_tile_shape": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _ip, _ip]),
+    "lbm_set_launch": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int]),
+    "lbm_get_launch": (ctypes.c_int, [_vp, _ip, _ip, _ip]),
+    "lbm_destroy": (ctypes.c_int, [_vp]),
+    "lbm_coexistence": (ctypes.c_int, [ctypes.c_double] * 3 + [_dp, _dp]),
+    "lbm_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+}
+for _name, (_res, _args) in _sig.items():
+    _f = getattr(_L, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+EXPORTED = tuple(_sig)
+
+
+def _check(rc, where):
+    if rc != OK:
+        raise LBMError(rc, where)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        return ctypes.c_void_p(int(t))
+    if not t.is_cuda:
+        raise ValueError("device tensor expected")
+    if not t.is_contiguous():
+        raise ValueError("contiguous tensor expected")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+# ---- one function per C entry point -----------------------------------------
+
+def lbm_strerror(code):
+    return _L.lbm_strerror(int(code)).decode()
+
+
+def lbm_params_default(**over):
+    p = lbm_params()
+    _L.lbm_params_default(ctypes.byref(p))
+    for k, v in over.items():
+        setattr(p, k, v)
+    return p
+
+
+def lbm_workspace_bytes(p):
+    return int(_L.lbm_workspace_bytes(ctypes.byref(p)))
+
+
+def lbm_init(p, workspace, rho0, u0=None, stream=None):
+    ctx = ctypes.c_void_p()
+    rc = _L.lbm_init(ctypes.byref(ctx), ctypes.byref(p), _ptr(workspace), workspace.numel() *
+                     workspace.element_size(), _stream(stream), _ptr(rho0), _ptr(u0))
+    _check(rc, "lbm_init")
+    return ctx
+
+
+def lbm_step(ctx, nsteps):
+    _check(_L.lbm_step(ctx, int(nsteps)), "lbm_step")
+
+
+def lbm_moments(ctx, rho=None, vel=None):
+    _check(_L.lbm_moments(ctx, _ptr(rho), _ptr(vel)), "lbm_moments")
+
+
+def lbm_max_spurious_u(ctx):
+    out = ctypes.c_double()
+    _check(_L.lbm_max_spurious_u(ctx, ctypes.byref(out)), "lbm_max_spurious_u")
+    return out.value
+
+
+def lbm_invariants(ctx):
+    m = ctypes.c_double()
+    mom = (ctypes.c_double * 3)()
+    _check(_L.lbm_invariants(ctx, ctypes.byref(m), mom), "lbm_invariants")
+    return m.value, [mom[0], mom[1], mom[2]]
+
+
+def lbm_step_observed(ctx, nsteps):
+    res, vmax = ctypes.c_double(), ctypes.c_double()
+    rc = _L.lbm_step_observed(ctx, int(nsteps), ctypes.byref(res), ctypes.byref(vmax))
+    if rc not in (OK, E_NONFINITE):
+        _check(rc, "lbm_step_observed")
+    return res.value, vmax.value, rc == OK
+
+
+def lbm_get_state(ctx, f):
+    _check(_L.lbm_get_state(ctx, _ptr(f)), "lbm_get_state")
+
+
+def lbm_set_state(ctx, f):
+    _check(_L.lbm_set_state(ctx, _ptr(f)), "lbm_set_state")
+
+
+def lbm_steps_done(ctx):
+    return int(_L.lbm_steps_done(ctx))
+
+
+def lbm_shift(ctx, q):
+    out = (ctypes.c_double * q)()
+    _check(_L.lbm_shift(ctx, out), "lbm_shift")
+    return list(out)
+
+
+def lbm_tile_count(lattice):
+    return int(_L.lbm_tile_count(int(lattice)))
+
+
+def lbm_tile_shape(lattice, k):
+    tx, ty = ctypes.c_int(), ctypes.c_int()
+    _check(_L.lbm_tile_shape(int(lattice), int(k), ctypes.byref(tx), ctypes.byref(ty)),
+           "lbm_tile_shape")
+    return tx.value, ty.value
+
+
+def lbm_set_launch(ctx, tile=-1, planes=0):
+    _check(_L.lbm_set_launch(ctx, int(tile), int(planes)), "lbm_set_launch")
+
+
+def lbm_get_launch(ctx):
+    t, p, w = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    _check(_L.lbm_get_launch(ctx, ctypes.byref(t), ctypes.byref(p), ctypes.byref(w)),
+           "lbm_get_launch")
+    return t.value, p.value, w.value
+
+
+def lbm_destroy(ctx):
+    _check(_L.lbm_destroy(ctx), "lbm_destroy")
+
+
+def lbm_coexistence(a, b, T):
+    g, l = ctypes.c_double(), ctypes.c_double()
+    _check(_L.lbm_coexistence(float(a), float(b), float(T), ctypes.byref(g), ctypes.byref(l)),
+           "lbm_coexistence")
+    return g.value, l.value
+
+
+# ---- convenience owner ------------------------------------------------------
+
+class Simulation:
+    """Owns one context and its workspace.  rho0 / u0 may be numpy arrays or
+    torch tensors ([nz][ny][nx] or [ny][nx], and [3][...] for u0)."""
+
+    def __init__(self, params, rho0, u0=None, device="cuda", stream=None):
+        self.p = params
+        self.q = params.lattice
+        self.n = params.nx * params.ny * params.nz
+        self.device = torch.device(device)
+        nbytes = lbm_workspace_bytes(params)
+        if nbytes == 0:
+            raise LBMError(E_INVAL, "lbm_workspace_bytes")
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        r = torch.as_tensor(rho0, dtype=torch.float64).reshape(-1).to(self.device).contiguous()
+        u = None
+        if u0 is not None:
+            u = torch.as_tensor(u0, dtype=torch.float64).reshape(3, -1).to(self.device).contiguous()
+        self.stream = stream
+        self.ctx = lbm_init(params, self.ws, r, u, stream)
+
+    def step(self, n):
+        lbm_step(self.ctx, n)
+
+    def moments(self):
+        rho = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        vel = torch.empty(3, self.n, dtype=torch.float64, device=self.device)
+        lbm_moments(self.ctx, rho, vel)
+        return rho, vel
+
+    def max_spurious_u(self):
+        return lbm_max_spurious_u(self.ctx)
+
+    def invariants(self):
+        return lbm_invariants(self.ctx)
+
+    def step_observed(self, n):
+        return lbm_step_observed(self.ctx, n)
+
+    def get_state(self):
+        f = torch.empty(self.q, self.n, dtype=torch.float64, device=self.device)
+        lbm_get_state(self.ctx, f)
+        return f
+
+    def set_state(self, f):
+        f = torch.as_tensor(f, dtype=torch.float64).reshape(self.q, self.n).to(self.device)
+        lbm_set_state(self.ctx, f.contiguous())
+
+    def shift(self):
+        return lbm_shift(self.ctx, self.q)
+
+    def set_launch(self, tile=-1, planes=0):
+        lbm_set_launch(self.ctx, tile, planes)
+
+    def launch(self):
+        return lbm_get_launch(self.ctx)
+
+    @property
+    def steps_done(self):
+        return lbm_steps_done(self.ctx)
+
+    def close(self):
+        if self.ctx is not None:
+            lbm_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def params(lattice=D2Q9, scheme=SCHEME_EQ, storage=STORE_F64, shape=(64, 64), a=9 / 49,
+           b=2 / 21, T=0.56, kappa=0.025, tau=1.0, **over):
+    """lbm_params from keyword arguments; shape = (nx, ny[, nz])."""
+    nz = shape[2] if len(shape) > 2 else 1
+    p = lbm_params_default(a=a, b=b, T=T, kappa=kappa, tau=tau, lattice=lattice, scheme=scheme,
+                           storage=storage, nx=shape[0], ny=shape[1], nz=nz)
+    for k, v in over.items():
+        setattr(p, k, v)
+    return p
+
+
+NAN = math.nan
