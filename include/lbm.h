@@ -182,6 +182,73 @@ int lbm_destroy(lbm_ctx *ctx);
  * (Maxwell construction).  Host computation.  LBM_E_INVAL if T >= T_c. */
 int lbm_coexistence(double a, double b, double T, double *rho_gas, double *rho_liq);
 
+/* ---- many independent problems in one launch per step -------------------
+ *
+ * A batch holds nprob independent periodic problems that share lattice,
+ * scheme, storage and compute (each has its own extent, a, b, T, kappa,
+ * tau, stencil overrides and shift).  Problem k's sites occupy
+ * [lbm_batch_offset(k), lbm_batch_offset(k+1)) of concatenated FP64 fields:
+ * a scalar field is [n_total], a vector field [3][n_total], each segment x
+ * fastest as in the single-problem API.  Every step is one persistent
+ * launch over a flat list of (problem, tile, plane chunk) work items; a
+ * problem that has been retired (converged, diverging, non-finite, out of
+ * steps) is skipped and keeps its state.  lbm_batch_run captures K steps
+ * plus the convergence check in a hipGraph and replays it; it needs a
+ * non-default stream (graph capture). */
+typedef struct lbm_batch lbm_batch;
+
+enum {
+    LBM_BATCH_RUNNING = 0,
+    LBM_BATCH_CONVERGED = 1,  /* residual <= tol                              */
+    LBM_BATCH_MAXSTEPS = 2,   /* max_steps reached first                      */
+    LBM_BATCH_DIVERGED = 3,   /* residual rose at `patience` consecutive checks */
+    LBM_BATCH_NONFINITE = 4   /* non-finite state or b*rho >= 1              */
+};
+
+/* Workspace bytes for these problems (0 if any is invalid or they do not
+ * share lattice, scheme, storage and compute). */
+size_t lbm_batch_workspace_bytes(int nprob, const lbm_params *per_problem);
+
+/* Create a batch and set every problem to the equilibrium of its initial
+ * density dev_rho0 [n_total] and velocity dev_u0 [3][n_total] (may be NULL).
+ * The launch shape comes from per_problem[0].tile / planes_per_block.
+ * stream must be a non-default hipStream_t.  Synchronises. */
+int lbm_batch_init(lbm_batch **out, int nprob, const lbm_params *per_problem,
+                   void *dev_workspace, size_t bytes, void *stream,
+                   const double *dev_rho0, const double *dev_u0);
+
+/* Advance every active problem by nsteps (no checks).  Only enqueues. */
+int lbm_batch_step(lbm_batch *bt, long long nsteps);
+
+/* Run until no problem is active or max_steps more steps have been taken.
+ * Every K = check_every (rounded up to even) steps each active problem's
+ * residual max_r |vel(r,t+1) - vel(r,t)| (vel as in lbm_moments, FP64) is
+ * measured; the problem is retired as LBM_BATCH_CONVERGED when it is <= tol,
+ * LBM_BATCH_DIVERGED when it rose at `patience` consecutive checks after
+ * `grace` steps (patience <= 0 disables this), LBM_BATCH_NONFINITE on a bad
+ * state, LBM_BATCH_MAXSTEPS when its step count reaches max_steps.
+ * Per-problem outputs (host, may be NULL): steps taken while active, last
+ * residual, status.  Synchronises once per K steps (4 bytes read back). */
+int lbm_batch_run(lbm_batch *bt, double tol, int check_every, long long max_steps, int patience,
+                  long long grace, long long *host_steps, double *host_residual, int *host_status);
+
+/* Density [n_total] and velocity [3][n_total] of every problem (retired ones
+ * included).  Only enqueues. */
+int lbm_batch_moments(lbm_batch *bt, double *dev_rho, double *dev_vel);
+
+/* First site of problem k in the concatenated fields (k = nprob gives
+ * n_total); -1 for a bad k. */
+long long lbm_batch_offset(const lbm_batch *bt, int k);
+
+/* Launch shape of the batched step (as lbm_set_launch) and the number of
+ * work items it makes. */
+int lbm_batch_set_launch(lbm_batch *bt, int tile, int planes_per_block);
+int lbm_batch_get_launch(const lbm_batch *bt, int *tile, int *planes_per_block, int *items);
+
+/* Free the batch (host memory and its graph; the workspace stays the
+ * caller's). */
+int lbm_batch_destroy(lbm_batch *bt);
+
 /* Human-readable name of a status code. */
 const char *lbm_strerror(int code);
 

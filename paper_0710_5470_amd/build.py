@@ -24,15 +24,15 @@ HIP_FLAGS = [
 ]
 
 
-def build(verbose=False, extra=()):
-    os.makedirs(LIBDIR, exist_ok=True)
-    tmp = LIB + ".tmp"
+def build(verbose=False, extra=(), out=LIB):
+    os.makedirs(os.path.dirname(out), exist_ok=True)
+    tmp = out + ".tmp"
     cmd = [HIPCC] + HIP_FLAGS + list(extra) + SOURCES + ["-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

@@ -14,8 +14,9 @@ namespace lbm {
 constexpr int RED_THREADS = 256;
 
 struct Geom {
-    int nx, ny, np;  // in-plane x, in-plane y (1 for D2Q9), planes
-    long long n;
+    int nx, ny, np;    // in-plane x, in-plane y (1 for D2Q9), planes
+    long long n;       // sites
+    long long stride;  // elements between direction (or component) arrays
 };
 
 template <class L> __device__ __forceinline__ void site_coords(const Geom &g, long long s, int &x,
@@ -66,14 +67,14 @@ __global__ void init_kernel(Geom g, Coefs<double> c, const double *__restrict__ 
     double j[3] = {0, 0, 0};
     if (u0) {
         j[0] = rho * u0[s];
-        j[1] = rho * u0[g.n + s];
-        if (L::DIM == 3) j[2] = rho * u0[2 * g.n + s];
+        j[1] = rho * u0[g.stride + s];
+        if (L::DIM == 3) j[2] = rho * u0[2 * g.stride + s];
     }
     double feq[L::Q];
-    equilibrium<L, SCHEME == SCHEME_EQ>(c, rho, j, d, lap, feq);
+    equilibrium<L, SCHEME == SCHEME_EQ>(c, rho - c.shift_sum, j, d, lap, feq);
 #pragma unroll
     for (int i = 0; i < L::Q; i++)
-        dst[(long long)i * g.n + neighbour<L>(g, x, y, p, i, -1)] = S(feq[i] - c.shift[i]);
+        dst[(long long)i * g.stride + neighbour<L>(g, x, y, p, i, -1)] = S(feq[i]);
 }
 
 // post-streaming populations f_i(r) = S[i][r - e_i] + s_i, FP64 [q][n]
@@ -87,8 +88,8 @@ __global__ void get_state_kernel(Geom g, Coefs<double> c, const S *__restrict__ 
     site_coords<L>(g, s, x, y, p);
 #pragma unroll
     for (int i = 0; i < L::Q; i++)
-        out[(long long)i * g.n + s] =
-            double(src[(long long)i * g.n + neighbour<L>(g, x, y, p, i, -1)]) + c.shift[i];
+        out[(long long)i * g.stride + s] =
+            double(src[(long long)i * g.stride + neighbour<L>(g, x, y, p, i, -1)]) + c.shift[i];
 }
 
 template <class L, class S>
@@ -101,8 +102,8 @@ __global__ void set_state_kernel(Geom g, Coefs<double> c, const double *__restri
     site_coords<L>(g, s, x, y, p);
 #pragma unroll
     for (int i = 0; i < L::Q; i++)
-        dst[(long long)i * g.n + neighbour<L>(g, x, y, p, i, -1)] =
-            S(in[(long long)i * g.n + s] - c.shift[i]);
+        dst[(long long)i * g.stride + neighbour<L>(g, x, y, p, i, -1)] =
+            S(in[(long long)i * g.stride + s] - c.shift[i]);
 }
 
 // ---- reductions -------------------------------------------------------------
@@ -153,7 +154,7 @@ __global__ __launch_bounds__(RED_THREADS) void reduce_pops_kernel(Geom g, const 
     long long stride = (long long)gridDim.x * RED_THREADS;
     for (long long s = (long long)blockIdx.x * RED_THREADS + threadIdx.x; s < g.n; s += stride)
 #pragma unroll
-        for (int i = 0; i < Q; i++) v[i] += double(src[(long long)i * g.n + s]);
+        for (int i = 0; i < Q; i++) v[i] += double(src[(long long)i * g.stride + s]);
     block_reduce<Q>(v, ops);
     if (threadIdx.x == 0)
 #pragma unroll

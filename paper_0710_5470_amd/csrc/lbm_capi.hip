@@ -49,7 +49,9 @@ bool valid_params(const lbm_params *p)
     if (p->compute != LBM_COMPUTE_NATIVE && p->compute != LBM_COMPUTE_F64) return false;
     if (p->nx < 1 || p->ny < 1 || p->nz < 1) return false;
     if (p->lattice == LBM_D2Q9 && p->nz != 1) return false;
-    if ((double)p->nx * p->ny * p->nz * p->lattice >= 9.0e18 / 8) return false;
+    // a population buffer is addressed with 32-bit byte offsets
+    double es = p->storage == LBM_STORE_F64 ? 8.0 : 4.0;
+    if ((double)p->nx * p->ny * p->nz * es * p->lattice >= 4294967296.0) return false;
     if (!(p->tau > 0.5) || !std::isfinite(p->tau)) return false;
     if (!(p->T > 0.0) || !std::isfinite(p->T)) return false;
     if (!(p->a >= 0.0) || !(p->b >= 0.0) || !(p->kappa >= 0.0)) return false;
@@ -151,6 +153,8 @@ Coefs<double> make_coefs(const lbm_params *p)
     c.omega = 1.0 / p->tau;
     c.nu = (p->tau - 0.5) / 3.0;
     c.lambda_on = p->galilean_lambda ? 1 : 0;
+    c.wp_ax_d = c.wp_ax;
+    c.wp_off_d = c.wp_off;
     return c;
 }
 
@@ -188,13 +192,13 @@ Coefs<float> to_float(const Coefs<double> &d)
     f.wt_ax = float(d.wt_ax); f.wt_off = float(d.wt_off);
     f.wm_para = float(d.wm_para); f.wm_perp = float(d.wm_perp);
     f.wm_in = float(d.wm_in); f.wm_out = float(d.wm_out);
-    f.a = float(d.a); f.b = float(d.b); f.T = float(d.T); f.kappa = float(d.kappa);
-    f.omega = float(d.omega); f.nu = float(d.nu); f.lambda_on = d.lambda_on;
-    for (int i = 0; i < 19; i++) f.shift[i] = float(d.shift[i]);
-    // the FP32 density adds the sum of the rounded shifts
-    double s = 0.0;
-    for (int i = 0; i < 19; i++) s += double(f.shift[i]);
-    f.shift_sum = float(s);
+    f.kappa = float(d.kappa);
+    f.omega = float(d.omega);
+    f.lambda_on = d.lambda_on;
+    f.a = d.a; f.b = d.b; f.T = d.T; f.nu = d.nu;
+    f.wp_ax_d = d.wp_ax_d; f.wp_off_d = d.wp_off_d;
+    for (int i = 0; i < 19; i++) f.shift[i] = d.shift[i];
+    f.shift_sum = d.shift_sum;
     return f;
 }
 
@@ -298,7 +302,7 @@ void launch_step(lbm_ctx *c, const void *src, void *dst, int write, int observe,
     if (d3 && fo) launch_step_l<D3Q19, SCHEME_FORCE>(c, src, dst, write, observe, orho, ovel);
 }
 
-Geom geom(const lbm_ctx *c) { return Geom{c->nx, c->ny, c->np, c->n}; }
+Geom geom(const lbm_ctx *c) { return Geom{c->nx, c->ny, c->np, c->n, c->n}; }
 
 unsigned grid1(long long n) { return unsigned((n + 255) / 256); }
 
@@ -594,7 +598,7 @@ int lbm_shift(const lbm_ctx *c, double *host_shift)
 {
     if (!c || !host_shift) return LBM_E_INVAL;
     for (int i = 0; i < c->p.lattice; i++)
-        host_shift[i] = c->p.storage == LBM_STORE_F64 ? 0.0 : double(c->cf.shift[i]);
+        host_shift[i] = c->cd.shift[i];
     return LBM_OK;
 }
 
@@ -682,3 +686,5 @@ int lbm_coexistence(double a, double b, double T, double *rho_gas, double *rho_l
 }
 
 } // extern "C"
+
+#include "lbm_batch_host.h"

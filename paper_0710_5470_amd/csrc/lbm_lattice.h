@@ -59,12 +59,18 @@ template <class R> struct Coefs {
     // w^aa: velocity along a (axis), axis velocity not along a,
     // off-axis velocity touching a, off-axis velocity not touching a (3D)
     R wm_para, wm_perp, wm_in, wm_out;
-    R a, b, T, kappa;
+    R kappa;
     R omega;           // 1 / tau
-    R nu;              // (tau - 1/2) / 3, Eq. (viscous)
     int lambda_on;
-    R shift[19];       // FP32 storage shift s_i (0 for FP64 storage)
-    R shift_sum;       // sum_i s_i
+    // Always FP64: the van der Waals pressure is a small difference of two
+    // large terms near coexistence (rho T/(1 - b rho) ~ a rho^2 ~ 4 in the
+    // liquid), so it, c_s^2 and the static part of each equilibrium
+    // population are evaluated in FP64 whatever R is.
+    double a, b, T;
+    double nu;         // (tau - 1/2) / 3, Eq. (viscous)
+    double wp_ax_d, wp_off_d;
+    double shift[19];  // FP32 storage shift s_i (0 for FP64 storage)
+    double shift_sum;  // sum_i s_i
 };
 
 template <class L, class R> __device__ __forceinline__ R coef_grad(const Coefs<R> &c, int i)
@@ -80,29 +86,35 @@ template <class L, class R> __device__ __forceinline__ R coef_force(const Coefs<
     return nnz<L>(i) == 1 ? c.Ef : c.Ff;
 }
 
-// van der Waals bulk pressure, Eq. (p0), and c_s^2 = dp0/drho.
-template <class R> __device__ __forceinline__ R vdw_p0(const Coefs<R> &c, R rho)
+// van der Waals bulk pressure, Eq. (p0), and c_s^2 = dp0/drho (FP64).
+template <class R> __device__ __forceinline__ double vdw_p0(const Coefs<R> &c, double rho)
 {
-    return rho * c.T / (R(1) - c.b * rho) - c.a * rho * rho;
+    return rho * c.T / (1.0 - c.b * rho) - c.a * rho * rho;
 }
-template <class R> __device__ __forceinline__ R vdw_cs2(const Coefs<R> &c, R rho)
+template <class R> __device__ __forceinline__ double vdw_cs2(const Coefs<R> &c, double rho)
 {
-    R d = R(1) - c.b * rho;
-    return c.T / (d * d) - R(2) * c.a * rho;
+    double d = 1.0 - c.b * rho;
+    return c.T / (d * d) - 2.0 * c.a * rho;
 }
 
-// Equilibrium of Eq. (equilibrium) for i >= 1 and Eq. (feq0) for i = 0.
-// j: momentum, d: discrete gradient of rho, lap: discrete Laplacian.
-// WITH_M adds the kappa d_a rho d_b rho terms (equilibrium scheme only).
+// Equilibrium of Eq. (equilibrium) for i >= 1 and Eq. (feq0) for i = 0,
+// returned as deviations from the storage shift: out_i = f_i^eq - s_i.
+// rho_dev = rho - sum_i s_i (rho itself when s = 0); j: momentum;
+// d: discrete gradient of rho; lap: discrete Laplacian.  The rest
+// deviation is rho_dev - sum_{i>=1} out_i, so the shift never enters the
+// mass balance.  WITH_M adds the kappa d_a rho d_b rho terms (equilibrium
+// scheme only).  Returns rho.
 template <class L, bool WITH_M, class R>
-__device__ __forceinline__ void equilibrium(const Coefs<R> &c, R rho, const R j[3], const R d[3],
-                                            R lap, R feq[L::Q])
+__device__ __forceinline__ R equilibrium(const Coefs<R> &c, R rho_dev, const R j[3], const R d[3],
+                                         R lap, R feq[L::Q])
 {
     constexpr int DIM = L::DIM;
+    const double rho_d = double(rho_dev) + c.shift_sum;
+    const R rho = R(rho_d);
     R inv_rho = R(1) / rho;
     R u[3] = {j[0] * inv_rho, j[1] * inv_rho, DIM == 3 ? j[2] * inv_rho : R(0)};
-    R p0 = vdw_p0(c, rho);
-    R lam = c.lambda_on ? c.nu * (R(1) - R(3) * vdw_cs2(c, rho)) : R(0);
+    const double p0 = vdw_p0(c, rho_d);
+    R lam = c.lambda_on ? R(c.nu * (1.0 - 3.0 * vdw_cs2(c, rho_d))) : R(0);
     R ud = u[0] * d[0] + u[1] * d[1] + (DIM == 3 ? u[2] * d[2] : R(0));
     R uu = u[0] * u[0] + u[1] * u[1] + (DIM == 3 ? u[2] * u[2] : R(0));
     // trace of X_ab = rho u_a u_b + lam (u_a d_b + u_b d_a + delta_ab u.d)
@@ -125,7 +137,9 @@ __device__ __forceinline__ void equilibrium(const Coefs<R> &c, R rho, const R j[
         R eXe = rho * eu * eu + lam * (R(2) * eu * ed + ee * ud);
         R w = axis ? c.w_ax : c.w_off;
         R v = w * (ej + R(1.5) * (eXe - trX * R(1.0 / 3.0)));
-        v += (axis ? c.wp_ax : c.wp_off) * p0 - (axis ? c.wt_ax : c.wt_off) * klap;
+        // static part w^p_i p0 - s_i in FP64, then the gradient terms
+        v += R((axis ? c.wp_ax_d : c.wp_off_d) * p0 - c.shift[i]);
+        v -= (axis ? c.wt_ax : c.wt_off) * klap;
         if (WITH_M) {
             R m = R(0);
 #pragma unroll
@@ -143,7 +157,8 @@ __device__ __forceinline__ void equilibrium(const Coefs<R> &c, R rho, const R j[
         feq[i] = v;
         sum += v;
     }
-    feq[0] = rho - sum;
+    feq[0] = rho_dev - sum;
+    return rho;
 }
 
 // Forcing term of Section "Using a forcing method":

@@ -8,16 +8,23 @@
 //
 // One workgroup owns a TX x TY tile of a plane and marches through `cp`
 // consecutive planes (D2Q9: rows along y, TY = 1; D3Q19: xy-planes along z).
-// Density planes of the tile plus an H-site halo (H = 1 for the equilibrium
-// scheme, H = 2 for the forcing scheme, whose force needs gradients one site
-// beyond the tile) live in an LDS ring; for the forcing scheme a second ring
-// holds the gradient of rho on the tile plus one site.  Each thread keeps the
-// pulled populations of its own site in registers from the plane where they
-// are loaded (H planes ahead) until that plane is collided.  Halo densities
-// are recomputed from populations owned by neighbouring tiles (they come from
-// L2 / MALL when the neighbours run concurrently, which the XCD-aware block
-// order encourages).
+// Densities (as rho - sum_i s_i) of the tile plus an H-site halo (H = 1 for
+// the equilibrium scheme, H = 2 for the forcing scheme, whose force needs
+// gradients one site beyond the tile) live in an LDS ring; for the forcing
+// scheme a second ring holds the gradient of rho on the tile plus one site.
+// Each thread keeps the pulled populations of its own site in registers from
+// the plane where they are loaded (H planes ahead) until that plane is
+// collided.  Halo densities are recomputed from populations owned by
+// neighbouring tiles (they come from L2 / MALL when the neighbours run
+// concurrently, which the XCD-aware workgroup order encourages).
+//
+// Population arrays are read and written through buffer resources (one per
+// direction, 32-bit byte offsets, hardware range check), with all wrapped
+// neighbour offsets precomputed per thread, so the per-load address work is
+// two integer adds.
 #pragma once
+
+#include <type_traits>
 
 #include "lbm_lattice.h"
 
@@ -29,7 +36,7 @@ template <class R> struct StepArgs {
     double *obs_rho;   // observation outputs (observe != 0)
     double *obs_vel;   // [3][n]
     int nx, ny, np;    // in-plane x, in-plane y (1 for D2Q9), number of planes
-    long long n;       // sites
+    long long n;       // sites; Q * n * sizeof(S) < 2^32 (checked by the host)
     int cp;            // planes per workgroup
     int tiles_x, tiles_y, chunks;
     int write_pops;    // store the collided populations into dst
@@ -37,13 +44,55 @@ template <class R> struct StepArgs {
     Coefs<R> c;
 };
 
-template <class S, class R> __device__ __forceinline__ R ld(const S *p, long long k)
+// Raw buffer descriptor over `bytes` bytes from base (gfx9 family dword3:
+// 32-bit data format, no swizzle).  One descriptor covers all directions of
+// a population buffer; the direction offset rides in the scalar offset.
+template <class S> __device__ __forceinline__ __amdgpu_buffer_rsrc_t pop_rsrc(const S *base, unsigned bytes)
 {
-    return R(p[k]);
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<S *>(base), (short)0, (int)bytes, 0x00020000);
 }
 
+__device__ __forceinline__ float buf_load(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, float)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+}
+__device__ __forceinline__ double buf_load(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, double)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
+}
+__device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, float v)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)voff, (int)soff, 0);
+}
+__device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, double v)
+{
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(decltype(__builtin_amdgcn_raw_buffer_load_b64(
+                                              r, 0, 0, 0)), v),
+                                          r, (int)voff, (int)soff, 0);
+}
+
+#ifndef LBM_STEP_WAVES_PER_EU
+#define LBM_STEP_WAVES_PER_EU 1
+#endif
+
+// One workgroup's share of a step: the tile at (x0, y0) of planes
+// [p0, p0 + npl) of one problem.
+template <class R> struct Job {
+    const void *src;       // direction i of this problem at src + i * stride
+    void *dst;
+    long long stride;      // elements between direction arrays
+    unsigned bytes;        // bytes addressable from src / dst (range check)
+    double *obs_rho;       // [n]
+    double *obs_vel;       // component a at obs_vel + a * obs_stride
+    long long obs_stride;
+    int nx, ny, np;        // in-plane x, in-plane y (1 for D2Q9), planes
+    int n;                 // sites of this problem
+    int x0, y0, p0, npl;
+    int write_pops, observe;
+};
+
 template <class L, int SCHEME, class S, class R, int TX, int TY>
-__global__ __launch_bounds__(TX *TY) void step_kernel(StepArgs<R> A)
+__device__ __forceinline__ void step_tile(const Job<R> &J, const Coefs<R> &c)
 {
     constexpr int Q = L::Q;
     constexpr bool FORCE = SCHEME == SCHEME_FORCE;
@@ -57,83 +106,121 @@ __global__ __launch_bounds__(TX *TY) void step_kernel(StepArgs<R> A)
     constexpr int GPL = TXG * TYG;
     constexpr int NT = TX * TY;
     constexpr int NHALO = 2 * HY * TXH + 2 * H * TY;
+    constexpr int NHT = (NHALO + NT - 1) / NT;  // halo sites per thread
+    constexpr unsigned ES = sizeof(S);
 
     __shared__ R rho_s[NR * PL];
     __shared__ R grad_s[FORCE ? 3 * 3 * GPL : 1];
 
-    const S *__restrict__ src = static_cast<const S *>(A.src);
-    S *__restrict__ dst = static_cast<S *>(A.dst);
-    const Coefs<R> &c = A.c;
-    const int nx = A.nx, ny = A.ny, np = A.np;
-    const long long n = A.n;
-
-    // XCD-aware order: consecutive workgroup ids go to different XCDs, so
-    // give each XCD a contiguous run of tiles (neighbours share halos in L2).
-    int nb = A.tiles_x * A.tiles_y * A.chunks;
-    int b = blockIdx.x;
-    if ((nb & 7) == 0) b = (b & 7) * (nb >> 3) + (b >> 3);
-    const int tile_x = b % A.tiles_x;
-    const int tile_y = (b / A.tiles_x) % A.tiles_y;
-    const int chunk = b / (A.tiles_x * A.tiles_y);
-    const int x0 = tile_x * TX, y0 = tile_y * TY;
-    const int p0 = chunk * A.cp;
-    const int npl = min(A.cp, np - p0);
-    if (npl <= 0) return;
+    const S *src = static_cast<const S *>(J.src);
+    S *dst = static_cast<S *>(J.dst);
+    const long long stride = J.stride;
+    const int nx = J.nx, ny = J.ny, np = J.np;
+    const int n = J.n;
+    const int psz = nx * ny;  // elements per plane
+    const int x0 = J.x0, y0 = J.y0, p0 = J.p0, npl = J.npl;
+    const __amdgpu_buffer_rsrc_t rs = pop_rsrc(src, J.bytes);
+    const __amdgpu_buffer_rsrc_t rd = pop_rsrc(dst, J.bytes);
 
     const int tid = threadIdx.x;
     const int tx = tid % TX, ty = tid / TX;
-    // this thread's site (wrapped; out-of-range threads still fill LDS)
+    // Own site (wrapped; threads past a ragged edge still fill LDS but do not
+    // store).  X[k] / Y[k]: element offsets of x + k - 1 / y + k - 1.
+    int X[3], Y[3];
     const int gx = wrapg(x0 + tx, nx);
     const int gy = L::DIM == 3 ? wrapg(y0 + ty, ny) : 0;
+    X[0] = wrap1(gx - 1, nx); X[1] = gx; X[2] = wrap1(gx + 1, nx);
+    if (L::DIM == 3) {
+        Y[0] = wrap1(gy - 1, ny) * nx; Y[1] = gy * nx; Y[2] = wrap1(gy + 1, ny) * nx;
+    } else {
+        Y[0] = Y[1] = Y[2] = 0;
+    }
     const bool own = (x0 + tx < nx) && (L::DIM == 2 || y0 + ty < ny);
 
-    // pulled populations of the own site: fr[k] holds plane (collide + k)
-    R fr[H + 1][Q];
+    // Halo sites of this thread (fixed for the whole march).
+    int hX[NHT][3], hY[NHT][3], hL[NHT];
+    bool hv[NHT];
+#pragma unroll
+    for (int s = 0; s < NHT; s++) {
+        const int k = tid + s * NT;
+        hv[s] = k < NHALO;
+        int lx = 0, ly = 0;
+        if (k < HY * TXH) {
+            ly = k / TXH;
+            lx = k % TXH;
+        } else if (k < 2 * HY * TXH) {
+            const int kk = k - HY * TXH;
+            ly = TY + HY + kk / TXH;
+            lx = kk % TXH;
+        } else {
+            const int kk = k - 2 * HY * TXH;
+            const int cc = kk % (2 * H);
+            ly = HY + kk / (2 * H);
+            lx = cc < H ? cc : TX + cc;
+        }
+        if (!hv[s]) lx = ly = 0;
+        hL[s] = ly * TXH + lx;
+        const int hx = wrapg(x0 - H + lx, nx);
+        const int hy = L::DIM == 3 ? wrapg(y0 - HY + ly, ny) : 0;
+        hX[s][0] = wrap1(hx - 1, nx); hX[s][1] = hx; hX[s][2] = wrap1(hx + 1, nx);
+        if (L::DIM == 3) {
+            hY[s][0] = wrap1(hy - 1, ny) * nx; hY[s][1] = hy * nx; hY[s][2] = wrap1(hy + 1, ny) * nx;
+        } else {
+            hY[s][0] = hY[s][1] = hY[s][2] = 0;
+        }
+    }
 
-    // pull the Q populations arriving at (x, y, plane p) and return rho
-    auto pull = [&](int x, int y, int p, R f[Q]) -> R {
-        R s = R(0);
+    // Pulled populations of the own site: fr[k] holds plane (collided + k)
+    // for k = 0..H; fr[H + 1] receives the next plane, whose loads are in
+    // flight while the current plane is collided (software pipelining: the
+    // memory latency of plane p + H + 1 overlaps the arithmetic of plane p).
+    // hr holds the in-flight halo populations of that next plane.
+    R fr[H + 2][Q];
+    R hr[NHT][Q];
+
+    // issue the Q loads of the populations arriving at the site with offsets
+    // (Xo, Yo) in the plane whose wrapped neighbour-plane offsets are P
+    auto pull = [&](const int(&Xo)[3], const int(&Yo)[3], const int(&P)[3], R(&f)[Q]) {
 #pragma unroll
         for (int i = 0; i < Q; i++) {
-            int xs = wrap1(x - ox<L>(i), nx);
-            int ys = L::DIM == 3 ? wrap1(y - oy<L>(i), ny) : 0;
-            int ps = wrap1(p - op<L>(i), np);
-            long long k = ((long long)ps * ny + ys) * nx + xs;
-            f[i] = ld<S, R>(src, (long long)i * n + k);
-            s += f[i];
+            const unsigned e = unsigned(P[1 - op<L>(i)] + Yo[1 - oy<L>(i)] + Xo[1 - ox<L>(i)]);
+            f[i] = R(buf_load(rs, e * ES, unsigned(i * stride) * ES, S()));
         }
-        return s + c.shift_sum;
+    };
+    // rho - sum_i s_i of pulled populations (fixed summation order)
+    auto dens = [&](const R(&f)[Q]) -> R {
+        R s = R(0);
+#pragma unroll
+        for (int i = 0; i < Q; i++) s += f[i];
+        return s;
+    };
+
+    auto plane_offsets = [&](int p, int(&P)[3]) {
+        P[0] = wrap1(p - 1, np) * psz;
+        P[1] = p * psz;
+        P[2] = wrap1(p + 1, np) * psz;
     };
 
     auto rho_at = [&](int lp, int lx, int ly) -> R & {
         return rho_s[(lp % NR) * PL + ly * TXH + lx];
     };
 
-    // density of local plane lp (global p0 - H + lp) on the tile + halo;
-    // the own site's pulled populations go to f
-    auto fill_rho = [&](int lp, R(&f)[Q]) {
-        int p = wrapg(p0 - H + lp, np);
-        rho_at(lp, tx + H, ty + HY) = pull(gx, gy, p, f);
-        for (int k = tid; k < NHALO; k += NT) {
-            int lx, ly;
-            if (k < HY * TXH) {
-                ly = k / TXH;
-                lx = k % TXH;
-            } else if (k < 2 * HY * TXH) {
-                int kk = k - HY * TXH;
-                ly = TY + HY + kk / TXH;
-                lx = kk % TXH;
-            } else {
-                int kk = k - 2 * HY * TXH;
-                int cc = kk % (2 * H);
-                ly = HY + kk / (2 * H);
-                lx = cc < H ? cc : TX + cc;
-            }
-            int hx = wrapg(x0 - H + lx, nx);
-            int hy = L::DIM == 3 ? wrapg(y0 - HY + ly, ny) : 0;
-            R g[Q];
-            rho_at(lp, lx, ly) = pull(hx, hy, p, g);
-        }
+    // local plane lp is global plane p0 - H + lp: issue the loads of its own
+    // site (into f) and halo sites (into hr), then store their densities
+    auto load_plane = [&](int lp, R(&f)[Q]) {
+        int P[3];
+        plane_offsets(wrapg(p0 - H + lp, np), P);
+        pull(X, Y, P, f);
+#pragma unroll
+        for (int s = 0; s < NHT; s++)
+            if (hv[s]) pull(hX[s], hY[s], P, hr[s]);
+    };
+    auto store_rho = [&](int lp, const R(&f)[Q]) {
+        R *ring = rho_s + (lp % NR) * PL;
+        ring[(ty + HY) * TXH + tx + H] = dens(f);
+#pragma unroll
+        for (int s = 0; s < NHT; s++)
+            if (hv[s]) ring[hL[s]] = dens(hr[s]);
     };
 
     // gradient of rho on the tile + 1 ring of local plane lp (forcing only)
@@ -142,8 +229,8 @@ __global__ __launch_bounds__(TX *TY) void step_kernel(StepArgs<R> A)
     };
     auto fill_grad = [&](int lp) {
         for (int k = tid; k < GPL; k += NT) {
-            int lx = k % TXG, ly = k / TXG;
-            int rx = lx + (H - 1), ry = ly + (HY - GY);
+            const int lx = k % TXG, ly = k / TXG;
+            const int rx = lx + (H - 1), ry = ly + (HY - GY);
             R d0 = R(0), d1 = R(0), d2 = R(0);
 #pragma unroll
             for (int i = 1; i < Q; i++) {
@@ -159,42 +246,54 @@ __global__ __launch_bounds__(TX *TY) void step_kernel(StepArgs<R> A)
         }
     };
 
-    // prologue: densities of planes p0-H .. p0+H-1, gradients of p0-1, p0
-    {
-        R tmp[Q];
-        for (int lp = 0; lp < H; lp++) fill_rho(lp, tmp);
+    // prologue: densities of planes p0-H .. p0+H (own populations of
+    // p0 .. p0+H kept in fr[0..H]), gradients of p0-1, p0
+    for (int lp = 0; lp < H; lp++) {
+        load_plane(lp, fr[H + 1]);
+        store_rho(lp, fr[H + 1]);
     }
-    fill_rho(H, fr[0]);
-    if constexpr (H == 2) fill_rho(H + 1, fr[1]);
+#pragma unroll
+    for (int s = 0; s <= H; s++) {
+        load_plane(H + s, fr[s]);
+        store_rho(H + s, fr[s]);
+    }
     __syncthreads();
     if (FORCE) {
         fill_grad(1);
         fill_grad(2);
     }
 
-    for (int k = 0; k < npl; k++) {
+    // One plane.  The register ring is indexed at compile time: plane H + k
+    // lives in fr[k mod (H + 2)], so the loop below is unrolled H + 2 times
+    // and no registers move between planes (moves of in-flight load targets
+    // would force waits at the loop head).
+    auto iteration = [&](const int k, auto phase) {
+        constexpr int RING = H + 2;
+        constexpr int C0 = decltype(phase)::value % RING;            // plane lc
+        constexpr int CN = (decltype(phase)::value + H + 1) % RING;  // plane lc + H + 1
         const int lc = H + k;  // local index of the plane collided now
-        fill_rho(lc + H, fr[H]);
-        __syncthreads();
+        const bool more = k + 1 < npl;
+        if (more) load_plane(lc + H + 1, fr[CN]);  // consumed after the collision
+        __syncthreads();  // densities up to plane lc + H are in LDS
         if (FORCE) {
             fill_grad(lc + 1);
             __syncthreads();
         }
         const int lx = tx + H, ly = ty + HY;
-        R rho = rho_at(lc, lx, ly);
+        const R rho_dev = rho_at(lc, lx, ly);
         R j[3] = {R(0), R(0), R(0)};
 #pragma unroll
         for (int i = 1; i < Q; i++) {
-            if (L::ex[i]) j[0] += R(L::ex[i]) * fr[0][i];
-            if (L::ey[i]) j[1] += R(L::ey[i]) * fr[0][i];
-            if (L::ez[i]) j[2] += R(L::ez[i]) * fr[0][i];
+            if (L::ex[i]) j[0] += R(L::ex[i]) * fr[C0][i];
+            if (L::ey[i]) j[1] += R(L::ey[i]) * fr[C0][i];
+            if (L::ez[i]) j[2] += R(L::ez[i]) * fr[C0][i];
         }
         R d[3] = {R(0), R(0), R(0)};
         R lap = R(0);
 #pragma unroll
         for (int i = 1; i < Q; i++) {
             R r = rho_at(lc + op<L>(i), lx + ox<L>(i), ly + oy<L>(i));
-            lap += coef_lap<L>(c, i) * (r - rho);
+            lap += coef_lap<L>(c, i) * (r - rho_dev);
             if (!FORCE) {
                 R cr = coef_grad<L>(c, i) * r;
                 if (L::ex[i]) d[0] += R(L::ex[i]) * cr;
@@ -228,38 +327,149 @@ __global__ __launch_bounds__(TX *TY) void step_kernel(StepArgs<R> A)
             g[2] *= -c.kappa;
         }
         R feq[Q];
-        equilibrium<L, !FORCE>(c, rho, j, d, lap, feq);
+        const R rho = equilibrium<L, !FORCE>(c, rho_dev, j, d, lap, feq);
         R F[Q];
         R inv_rho = R(1) / rho;
         R u[3] = {j[0] * inv_rho, j[1] * inv_rho, j[2] * inv_rho};
         if (FORCE) forcing<L>(c, u, g, F);
         const int p = wrapg(p0 + k, np);
-        const long long site = ((long long)p * ny + gy) * nx + gx;
-        if (own && A.write_pops) {
+        const unsigned site = unsigned(p * psz + Y[1] + X[1]);
+        // collided populations (stored below)
+        R out[Q];
 #pragma unroll
-            for (int i = 0; i < Q; i++) {
-                R dlt = fr[0][i];
-                R out = dlt + c.omega * (feq[i] - c.shift[i] - dlt);
-                if (FORCE) out += F[i];
-                dst[(long long)i * n + site] = S(out);
-            }
+        for (int i = 0; i < Q; i++) {
+            R dlt = fr[C0][i];
+            out[i] = dlt + c.omega * (feq[i] - dlt);
+            if (FORCE) out[i] += F[i];
         }
-        if (own && A.observe) {
-            A.obs_rho[site] = double(rho);
+        if (own && J.observe) {
+            J.obs_rho[site] = double(rho_dev) + c.shift_sum;
             R h = FORCE ? R(0.5) * inv_rho : R(0);
-            A.obs_vel[site] = double(u[0] + h * g[0]);
-            A.obs_vel[n + site] = double(u[1] + h * g[1]);
-            A.obs_vel[2 * n + site] = double(L::DIM == 3 ? u[2] + h * g[2] : R(0));
+            J.obs_vel[site] = double(u[0] + h * g[0]);
+            J.obs_vel[J.obs_stride + site] = double(u[1] + h * g[1]);
+            J.obs_vel[2 * J.obs_stride + site] = double(L::DIM == 3 ? u[2] + h * g[2] : R(0));
         }
-        // rotate the register ring
+        // Densities of the next plane: its ring slot (plane lc+H+1) is read by
+        // no thread in this iteration (ring depths 4 and 5), so no barrier is
+        // needed before this store; the next iteration's first barrier
+        // publishes it.  The next gradient fill overwrites a plane read above
+        // only after that barrier.
+        if (more) store_rho(lc + H + 1, fr[CN]);
+        // Global stores after the wait for the prefetched loads: memory
+        // counters retire in order, so a wait on a load issued before these
+        // stores would also wait for their write acknowledgements.
+        if (own && J.write_pops) {
 #pragma unroll
-        for (int s = 0; s < H; s++)
-#pragma unroll
-            for (int i = 0; i < Q; i++) fr[s][i] = fr[s + 1][i];
-        // No barrier here: the next density fill writes ring slot of plane
-        // lc+H+1, which no thread reads in this iteration (ring depths 4 and
-        // 5); the next gradient fill overwrites a plane read above only after
-        // the next barrier.
+            for (int i = 0; i < Q; i++) buf_store(rd, site * ES, unsigned(i * stride) * ES, S(out[i]));
+        }
+    };
+
+    for (int k = 0; k < npl; k += H + 2) {
+        iteration(k, std::integral_constant<int, 0>{});
+        if (k + 1 < npl) iteration(k + 1, std::integral_constant<int, 1>{});
+        if (k + 2 < npl) iteration(k + 2, std::integral_constant<int, 2>{});
+        if constexpr (H == 2) {
+            if (k + 3 < npl) iteration(k + 3, std::integral_constant<int, 3>{});
+        }
+    }
+}
+
+// One problem: workgroup b takes tile (b mod tiles_x, ...) of chunk b / tiles.
+template <class L, int SCHEME, class S, class R, int TX, int TY>
+__global__ __launch_bounds__(TX *TY) __attribute__((amdgpu_waves_per_eu(LBM_STEP_WAVES_PER_EU)))
+void step_kernel(StepArgs<R> A)
+{
+    // XCD-aware order: consecutive workgroup ids go to different XCDs, so
+    // give each XCD a contiguous run of tiles (neighbours share halos in L2).
+    const int nb = A.tiles_x * A.tiles_y * A.chunks;
+    int b = blockIdx.x;
+    if ((nb & 7) == 0) b = (b & 7) * (nb >> 3) + (b >> 3);
+    const int tile_x = b % A.tiles_x;
+    const int tile_y = (b / A.tiles_x) % A.tiles_y;
+    const int chunk = b / (A.tiles_x * A.tiles_y);
+    Job<R> J;
+    J.src = A.src;
+    J.dst = A.dst;
+    J.stride = A.n;
+    J.bytes = unsigned((long long)L::Q * A.n * (long long)sizeof(S));
+    J.obs_rho = A.obs_rho;
+    J.obs_vel = A.obs_vel;
+    J.obs_stride = A.n;
+    J.nx = A.nx;
+    J.ny = A.ny;
+    J.np = A.np;
+    J.n = int(A.n);
+    J.x0 = tile_x * TX;
+    J.y0 = tile_y * TY;
+    J.p0 = chunk * A.cp;
+    J.npl = min(A.cp, A.np - J.p0);
+    J.write_pops = A.write_pops;
+    J.observe = A.observe;
+    if (J.npl <= 0) return;
+    step_tile<L, SCHEME, S, R, TX, TY>(J, A.c);
+}
+
+// ---- many independent problems in one persistent launch --------------------
+
+struct BatchProblem {
+    long long off;       // first site of the problem in the concatenated arrays
+    int nx, ny, np;      // kernel geometry (D2Q9: ny = 1, np = lattice ny)
+    int tiles_x, tiles_y, chunks, cp;
+    int item0;           // first work item of the problem
+};
+
+template <class R> struct BatchArgs {
+    const void *src;
+    void *dst;
+    long long stride;             // total sites (elements between directions)
+    double *obs_rho, *obs_vel;    // concatenated observation fields
+    const BatchProblem *prob;     // [nprob]
+    const Coefs<R> *coefs;        // [nprob]
+    const int *active;            // [nprob]; 0 = skip (converged or stopped)
+    int nprob, nitems;
+    int write_pops, observe;
+};
+
+// Persistent grid: workgroup g takes work items g, g + G, ...; an item is
+// one tile x chunk of one problem (binary search over item0).  Items of
+// inactive problems are skipped, so converged problems keep their state.
+template <class L, int SCHEME, class S, class R, int TX, int TY>
+__global__ __launch_bounds__(TX *TY) __attribute__((amdgpu_waves_per_eu(LBM_STEP_WAVES_PER_EU)))
+void batch_step_kernel(BatchArgs<R> B)
+{
+    for (int w = blockIdx.x; w < B.nitems; w += gridDim.x) {
+        int lo = 0, hi = B.nprob - 1;
+        while (lo < hi) {
+            int mid = (lo + hi + 1) >> 1;
+            if (B.prob[mid].item0 <= w) lo = mid; else hi = mid - 1;
+        }
+        const int k = lo;
+        if (!B.active[k]) continue;
+        const BatchProblem P = B.prob[k];
+        const int item = w - P.item0;
+        const int tile_x = item % P.tiles_x;
+        const int tile_y = (item / P.tiles_x) % P.tiles_y;
+        const int chunk = item / (P.tiles_x * P.tiles_y);
+        Job<R> J;
+        J.src = static_cast<const S *>(B.src) + P.off;
+        J.dst = static_cast<S *>(B.dst) + P.off;
+        J.stride = B.stride;
+        J.bytes = unsigned(((long long)L::Q * B.stride - P.off) * (long long)sizeof(S));
+        J.obs_rho = B.obs_rho ? B.obs_rho + P.off : nullptr;
+        J.obs_vel = B.obs_vel ? B.obs_vel + P.off : nullptr;
+        J.obs_stride = B.stride;
+        J.nx = P.nx;
+        J.ny = P.ny;
+        J.np = P.np;
+        J.n = P.nx * P.ny * P.np;
+        J.x0 = tile_x * TX;
+        J.y0 = tile_y * TY;
+        J.p0 = chunk * P.cp;
+        J.npl = min(P.cp, P.np - J.p0);
+        J.write_pops = B.write_pops;
+        J.observe = B.observe;
+        step_tile<L, SCHEME, S, R, TX, TY>(J, B.coefs[k]);
+        __syncthreads();  // the LDS rings are reused by the next item
     }
 }
 

@@ -14,7 +14,7 @@ import os
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "_lib", "liblbm.so")
+LIB_PATH = os.environ.get("LBM_LIBRARY", os.path.join(_HERE, "_lib", "liblbm.so"))
 
 D2Q9, D3Q19 = 9, 19
 SCHEME_EQ, SCHEME_FORCE = 0, 1
@@ -73,7 +73,20 @@ _sig = {
     "lbm_destroy": (ctypes.c_int, [_vp]),
     "lbm_coexistence": (ctypes.c_int, [ctypes.c_double] * 3 + [_dp, _dp]),
     "lbm_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "lbm_batch_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int, _pp]),
+    "lbm_batch_init": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int, _pp, _vp, ctypes.c_size_t,
+                                      _vp, _vp, _vp]),
+    "lbm_batch_step": (ctypes.c_int, [_vp, ctypes.c_longlong]),
+    "lbm_batch_run": (ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_int, ctypes.c_longlong,
+                                     ctypes.c_int, ctypes.c_longlong,
+                                     ctypes.POINTER(ctypes.c_longlong), _dp, _ip]),
+    "lbm_batch_moments": (ctypes.c_int, [_vp, _vp, _vp]),
+    "lbm_batch_offset": (ctypes.c_longlong, [_vp, ctypes.c_int]),
+    "lbm_batch_set_launch": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int]),
+    "lbm_batch_get_launch": (ctypes.c_int, [_vp, _ip, _ip, _ip]),
+    "lbm_batch_destroy": (ctypes.c_int, [_vp]),
 }
+BATCH_RUNNING, BATCH_CONVERGED, BATCH_MAXSTEPS, BATCH_DIVERGED, BATCH_NONFINITE = 0, 1, 2, 3, 4
 for _name, (_res, _args) in _sig.items():
     _f = getattr(_L, _name)
     _f.restype = _res
@@ -211,7 +224,133 @@ def lbm_coexistence(a, b, T):
     return g.value, l.value
 
 
-# ---- convenience owner ------------------------------------------------------
+def _params_array(plist):
+    arr = (lbm_params * len(plist))()
+    for k, p in enumerate(plist):
+        arr[k] = p
+    return arr
+
+
+def lbm_batch_workspace_bytes(plist):
+    return int(_L.lbm_batch_workspace_bytes(len(plist), _params_array(plist)))
+
+
+def lbm_batch_init(plist, workspace, rho0, u0=None, stream=None):
+    if stream is None:
+        raise ValueError("a batch needs a non-default stream (graph capture)")
+    bt = ctypes.c_void_p()
+    rc = _L.lbm_batch_init(ctypes.byref(bt), len(plist), _params_array(plist), _ptr(workspace),
+                           workspace.numel() * workspace.element_size(), _stream(stream),
+                           _ptr(rho0), _ptr(u0))
+    _check(rc, "lbm_batch_init")
+    return bt
+
+
+def lbm_batch_step(bt, nsteps):
+    _check(_L.lbm_batch_step(bt, int(nsteps)), "lbm_batch_step")
+
+
+def lbm_batch_run(bt, nprob, tol, check_every, max_steps, patience=0, grace=0):
+    steps = (ctypes.c_longlong * nprob)()
+    res = (ctypes.c_double * nprob)()
+    status = (ctypes.c_int * nprob)()
+    _check(_L.lbm_batch_run(bt, float(tol), int(check_every), int(max_steps), int(patience),
+                            int(grace), steps, res, status), "lbm_batch_run")
+    return list(steps), list(res), list(status)
+
+
+def lbm_batch_moments(bt, rho, vel):
+    _check(_L.lbm_batch_moments(bt, _ptr(rho), _ptr(vel)), "lbm_batch_moments")
+
+
+def lbm_batch_offset(bt, k):
+    return int(_L.lbm_batch_offset(bt, int(k)))
+
+
+def lbm_batch_set_launch(bt, tile=-1, planes=0):
+    _check(_L.lbm_batch_set_launch(bt, int(tile), int(planes)), "lbm_batch_set_launch")
+
+
+def lbm_batch_get_launch(bt):
+    t, p, w = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    _check(_L.lbm_batch_get_launch(bt, ctypes.byref(t), ctypes.byref(p), ctypes.byref(w)),
+           "lbm_batch_get_launch")
+    return t.value, p.value, w.value
+
+
+def lbm_batch_destroy(bt):
+    _check(_L.lbm_batch_destroy(bt), "lbm_batch_destroy")
+
+
+# ---- convenience owners -----------------------------------------------------
+
+class Batch:
+    """Owns one batch, its workspace and a non-default stream.  rho0 / u0:
+    lists of per-problem arrays (or one concatenated array / tensor)."""
+
+    def __init__(self, plist, rho0, u0=None, device="cuda"):
+        self.plist = list(plist)
+        self.nprob = len(self.plist)
+        self.device = torch.device(device)
+        self.stream = torch.cuda.Stream(device=self.device)
+        nbytes = lbm_batch_workspace_bytes(self.plist)
+        if nbytes == 0:
+            raise LBMError(E_INVAL, "lbm_batch_workspace_bytes")
+        self.sizes = [p.nx * p.ny * p.nz for p in self.plist]
+        self.ntot = sum(self.sizes)
+        r = self._concat(rho0, 1)
+        u = self._concat(u0, 3) if u0 is not None else None
+        with torch.cuda.stream(self.stream):
+            self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream.wait_stream(torch.cuda.current_stream())
+        self.bt = lbm_batch_init(self.plist, self.ws, r, u, self.stream)
+        self.offsets = [lbm_batch_offset(self.bt, k) for k in range(self.nprob + 1)]
+
+    def _concat(self, a, ncomp):
+        if isinstance(a, (list, tuple)):
+            parts = [torch.as_tensor(x, dtype=torch.float64).reshape(ncomp, -1) for x in a]
+            t = torch.cat(parts, dim=1)
+        else:
+            t = torch.as_tensor(a, dtype=torch.float64).reshape(ncomp, -1)
+        assert t.shape[1] == self.ntot
+        return t.reshape(-1).to(self.device).contiguous() if ncomp == 1 else \
+            t.to(self.device).contiguous()
+
+    def run(self, tol, check_every=100, max_steps=10 ** 6, patience=0, grace=0):
+        return lbm_batch_run(self.bt, self.nprob, tol, check_every, max_steps, patience, grace)
+
+    def step(self, n):
+        lbm_batch_step(self.bt, n)
+
+    def moments(self):
+        with torch.cuda.stream(self.stream):
+            rho = torch.empty(self.ntot, dtype=torch.float64, device=self.device)
+            vel = torch.empty(3, self.ntot, dtype=torch.float64, device=self.device)
+        lbm_batch_moments(self.bt, rho, vel)
+        self.stream.synchronize()
+        return rho, vel
+
+    def split(self, field):
+        """Per-problem views of a concatenated field ([n] or [3][n])."""
+        return [field[..., self.offsets[k]:self.offsets[k + 1]] for k in range(self.nprob)]
+
+    def set_launch(self, tile=-1, planes=0):
+        lbm_batch_set_launch(self.bt, tile, planes)
+
+    def launch(self):
+        return lbm_batch_get_launch(self.bt)
+
+    def close(self):
+        if self.bt is not None:
+            self.stream.synchronize()
+            lbm_batch_destroy(self.bt)
+            self.bt = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 class Simulation:
     """Owns one context and its workspace.  rho0 / u0 may be numpy arrays or

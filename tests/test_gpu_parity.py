@@ -174,9 +174,15 @@ def test_fp32_storage_f32_math_within_derived_tolerance(q, scheme, shape, steps)
 
 
 def test_fp32_literal_weight_shift():
-    """The shift s_i = w_i rho0 with normalised lattice weights."""
+    """The shift s_i = w_i rho0 with normalised lattice weights (FP64
+    arithmetic).  Its deviations f_i - s_i are several times larger than
+    those from the rest-equilibrium shift (the moving populations sit near
+    w_i p0, not w_i rho0), so FP32 storage rounding leaves a larger velocity
+    error: held to 5e-8, and it must not beat the rest-equilibrium shift."""
     err_r, err_v = _fp32_case(9, 1, (64, 64), 300, compute=1, shift_mode=1)
-    assert err_r < 1e-5 and err_v < 1e-8
+    err_r0, err_v0 = _fp32_case(9, 1, (64, 64), 300, compute=1, shift_mode=0)
+    assert err_r < 1e-5 and err_v < 5e-8
+    assert err_v0 <= err_v
 
 
 def test_conservation_and_determinism_fp64():
