@@ -144,16 +144,28 @@ def sphere_with_noise(n, radius, rho_gas, rho_liq, amplitude, seed, width=2.0):
 
 
 def batch_specs(nprob, seed, side_lo=32, side_hi=256, frac_lo=0.15, frac_hi=0.35,
-                T_lo=0.45, T_hi=0.55, kappa_lo=0.005, kappa_hi=0.02):
+                T_lo=0.45, T_hi=0.55, kappa_lo=0.005, kappa_hi=0.02, kappa_cap=None):
     """Parameters of a batch of independent square D2Q9 problems: side
     uniform in {side_lo..side_hi}, radius uniform in [frac_lo, frac_hi] x side,
-    T and kappa uniform in their ranges."""
+    T uniform in [T_lo, T_hi], kappa uniform in [kappa_lo, kappa_hi] or, with
+    kappa_cap (a function of T), in [kappa_lo, min(kappa_hi, kappa_cap(T))]."""
     st = Stream(seed)
     out = []
     for _ in range(nprob):
         side = st.integers(side_lo, side_hi)
         frac = frac_lo + (frac_hi - frac_lo) * st.uniform()
         T = T_lo + (T_hi - T_lo) * st.uniform()
-        kappa = kappa_lo + (kappa_hi - kappa_lo) * st.uniform()
+        hi = kappa_hi if kappa_cap is None else min(kappa_hi, kappa_cap(T))
+        kappa = kappa_lo + (hi - kappa_lo) * st.uniform()
         out.append(dict(side=side, radius=frac * side, T=T, kappa=kappa))
     return out
+
+
+def stable_batch_specs(nprob, seed, side_lo=32, side_hi=256):
+    """The batched drop workload with temperatures and interface
+    coefficients moved into the range where the coexisting liquid is linearly
+    stable at tau = 1: T uniform in [0.54, 0.56] and kappa uniform in
+    [0.005, min(0.02, (T - 0.5) / 3)] (the uniform liquid at the Maxwell
+    density needs roughly T > 0.49 + 3 kappa)."""
+    return batch_specs(nprob, seed, side_lo=side_lo, side_hi=side_hi, T_lo=0.54, T_hi=0.56,
+                       kappa_cap=lambda T: (T - 0.5) / 3.0)

