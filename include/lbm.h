@@ -249,6 +249,56 @@ int lbm_batch_get_launch(const lbm_batch *bt, int *tile, int *planes_per_block, 
  * caller's). */
 int lbm_batch_destroy(lbm_batch *bt);
 
+/* ---- warm-start network kernels ------------------------------------------
+ *
+ * Building blocks of the small convolutional network that predicts a
+ * near-steady (rho, u) field from the drop parameters, so a batch can start
+ * close to its steady state.  3x3 convolutions wrap periodically in x and y
+ * (like the lattice).  They run as implicit GEMMs on bf16 matrix cores with
+ * FP32 accumulation: FP32 operands are rounded to bf16 (nearest even) as they
+ * enter the MFMA.  Tensors are FP32, NHWC, 16-byte aligned, with padded
+ * channel counts cin, cout in {16, 32}; nb * h * w must be a multiple of 16.
+ * Weights are [9][cout][cin] with tap 3 (dy + 1) + (dx + 1):
+ *   out[p][co] = bias[co] + sum_{tap, ci} W[tap][co][ci] act(in[p + (dy, dx)][ci])
+ * with act = max(., 0) when relu_in, else the identity.  Channels co >=
+ * cout_real are written as zero.  All functions only enqueue on `stream`
+ * except lbm_net_mse with a non-NULL host_loss, which synchronises. */
+typedef struct {
+    int nb, h, w;       /* images, rows, columns */
+    int cin, cout;      /* padded channel counts */
+    int cout_real;      /* channels actually produced */
+} lbm_conv_shape;
+
+int lbm_net_conv3x3_fwd(const lbm_conv_shape *s, const float *dev_in, int relu_in,
+                        const float *dev_w, const float *dev_bias, float *dev_out, void *stream);
+
+/* Gradient with respect to the convolution input:
+ * din[q][ci] = sum_{tap, co} W[tap][co][ci] dout[q - (dy, dx)][co], multiplied
+ * by (zin[q][ci] > 0) when dev_zin is not NULL (the previous layer's relu). */
+int lbm_net_conv3x3_bwd_data(const lbm_conv_shape *s, const float *dev_dout, const float *dev_w,
+                             const float *dev_zin, float *dev_din, void *stream);
+
+/* Workspace bytes for lbm_net_conv3x3_bwd_weight (per-workgroup partials). */
+size_t lbm_net_conv3x3_bwd_weight_workspace(const lbm_conv_shape *s);
+
+/* Gradients with respect to the weights [9][cout][cin] and bias [cout]:
+ * dW[tap][co][ci] = sum_p dout[p][co] act(in[p + (dy, dx)][ci]),
+ * dbias[co] = sum_p dout[p][co]; partial sums are combined in a fixed order
+ * (deterministic). */
+int lbm_net_conv3x3_bwd_weight(const lbm_conv_shape *s, const float *dev_dout, const float *dev_in,
+                               int relu_in, float *dev_dw, float *dev_dbias, void *dev_workspace,
+                               size_t bytes, void *stream);
+
+/* Mean squared error over the first creal of c channels of npix pixels;
+ * writes grad = 2 (pred - target) / (npix creal) (zero in padded channels)
+ * and, if host_loss is not NULL, the loss.  dev_part holds >= 1024 doubles. */
+int lbm_net_mse(long long npix, int c, int creal, const float *dev_pred, const float *dev_target,
+                float *dev_grad, double *dev_part, double *host_loss, void *stream);
+
+/* One Adam step (Kingma & Ba) on n parameters, step number t >= 1. */
+int lbm_net_adam(int n, float *dev_param, const float *dev_grad, float *dev_m, float *dev_v,
+                 double lr, double beta1, double beta2, double eps, long long t, void *stream);
+
 /* Human-readable name of a status code. */
 const char *lbm_strerror(int code);
 

@@ -1,0 +1,113 @@
+// lbm_net_host.h -- host side of the warm-start network kernels (included
+// once, at the end of lbm_capi.hip).
+
+#include "lbm_net.h"
+
+namespace {
+
+bool conv_ok(const lbm_conv_shape *s)
+{
+    if (!s || s->nb < 1 || s->h < 1 || s->w < 1) return false;
+    if (s->cin < 16 || s->cin > 32 || s->cin % 16) return false;
+    if (s->cout < 16 || s->cout > 32 || s->cout % 16) return false;
+    if (s->cout_real < 1 || s->cout_real > s->cout) return false;
+    long long npix = (long long)s->nb * s->h * s->w;
+    return npix % 16 == 0;
+}
+
+lbmnet::ConvShape conv_shape(const lbm_conv_shape *s)
+{
+    return lbmnet::ConvShape{s->nb, s->h, s->w, s->cin, s->cout, s->cout_real};
+}
+
+bool aligned16(const void *p) { return p && (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
+
+constexpr int NET_CHUNK = 1024;  // pixels per workgroup in the weight gradient
+
+unsigned conv_grid(const lbm_conv_shape *s)
+{
+    long long npix = (long long)s->nb * s->h * s->w;
+    return unsigned((npix / 16 + 3) / 4);
+}
+
+} // namespace
+
+extern "C" {
+
+int lbm_net_conv3x3_fwd(const lbm_conv_shape *s, const float *dev_in, int relu_in, const float *dev_w,
+                        const float *dev_b, float *dev_out, void *stream)
+{
+    if (!conv_ok(s) || !aligned16(dev_in) || !aligned16(dev_w) || !dev_b || !dev_out) return LBM_E_INVAL;
+    lbmnet::conv_fwd_kernel<<<conv_grid(s), lbmnet::NET_THREADS, 0, static_cast<hipStream_t>(stream)>>>(
+        conv_shape(s), dev_in, relu_in, dev_w, dev_b, dev_out);
+    return hipGetLastError() == hipSuccess ? LBM_OK : LBM_E_DEVICE;
+}
+
+int lbm_net_conv3x3_bwd_data(const lbm_conv_shape *s, const float *dev_dout, const float *dev_w,
+                             const float *dev_zin, float *dev_din, void *stream)
+{
+    if (!conv_ok(s) || !aligned16(dev_dout) || !dev_w || !dev_din) return LBM_E_INVAL;
+    lbmnet::conv_bwd_data_kernel<<<conv_grid(s), lbmnet::NET_THREADS, 0, static_cast<hipStream_t>(stream)>>>(
+        conv_shape(s), dev_dout, dev_w, dev_zin, dev_din);
+    return hipGetLastError() == hipSuccess ? LBM_OK : LBM_E_DEVICE;
+}
+
+size_t lbm_net_conv3x3_bwd_weight_workspace(const lbm_conv_shape *s)
+{
+    if (!conv_ok(s)) return 0;
+    long long npix = (long long)s->nb * s->h * s->w;
+    long long parts = (npix + NET_CHUNK - 1) / NET_CHUNK;
+    return size_t(parts) * 9 * s->cout * s->cin * sizeof(float);
+}
+
+int lbm_net_conv3x3_bwd_weight(const lbm_conv_shape *s, const float *dev_dout, const float *dev_in,
+                               int relu_in, float *dev_dw, float *dev_db, void *dev_ws, size_t ws_bytes,
+                               void *stream)
+{
+    if (!conv_ok(s) || !dev_dout || !dev_in || !dev_dw || !dev_db || !dev_ws) return LBM_E_INVAL;
+    if (ws_bytes < lbm_net_conv3x3_bwd_weight_workspace(s)) return LBM_E_NOMEM;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    long long npix = (long long)s->nb * s->h * s->w;
+    int parts = int((npix + NET_CHUNK - 1) / NET_CHUNK);
+    float *part = static_cast<float *>(dev_ws);
+    lbmnet::conv_bwd_weight_kernel<<<parts, lbmnet::NET_THREADS, 0, st>>>(conv_shape(s), dev_dout, dev_in,
+                                                                          relu_in, NET_CHUNK, part);
+    int len = 9 * s->cout * s->cin;
+    lbmnet::sum_parts_kernel<<<(len + 255) / 256, 256, 0, st>>>(parts, len, part, dev_dw);
+    lbmnet::bias_grad_kernel<<<s->cout, lbmnet::NET_THREADS, 0, st>>>(npix, s->cout, dev_dout, dev_db);
+    return hipGetLastError() == hipSuccess ? LBM_OK : LBM_E_DEVICE;
+}
+
+int lbm_net_mse(long long npix, int c, int creal, const float *dev_pred, const float *dev_target,
+                float *dev_grad, double *dev_part, double *host_loss, void *stream)
+{
+    if (npix < 1 || c < 1 || creal < 1 || creal > c || !dev_pred || !dev_target || !dev_grad || !dev_part)
+        return LBM_E_INVAL;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int nblk = 1024;
+    lbmnet::mse_kernel<<<nblk, lbmnet::NET_THREADS, 0, st>>>(npix, c, creal, dev_pred, dev_target, dev_grad,
+                                                             dev_part);
+    if (hipGetLastError() != hipSuccess) return LBM_E_DEVICE;
+    if (host_loss) {
+        double h[nblk];
+        if (hipMemcpyAsync(h, dev_part, sizeof(h), hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess)
+            return LBM_E_DEVICE;
+        double a = 0.0;
+        for (int k = 0; k < nblk; k++) a += h[k];
+        *host_loss = a;
+    }
+    return LBM_OK;
+}
+
+int lbm_net_adam(int n, float *dev_p, const float *dev_g, float *dev_m, float *dev_v, double lr, double b1,
+                 double b2, double eps, long long t, void *stream)
+{
+    if (n < 1 || !dev_p || !dev_g || !dev_m || !dev_v || t < 1) return LBM_E_INVAL;
+    double c1 = 1.0 - std::pow(b1, double(t)), c2 = 1.0 - std::pow(b2, double(t));
+    lbmnet::adam_kernel<<<(n + 255) / 256, 256, 0, static_cast<hipStream_t>(stream)>>>(
+        n, dev_p, dev_g, dev_m, dev_v, float(lr), float(b1), float(b2), float(eps), float(c1), float(c2));
+    return hipGetLastError() == hipSuccess ? LBM_OK : LBM_E_DEVICE;
+}
+
+} // extern "C"

@@ -86,6 +86,26 @@ _sig = {
     "lbm_batch_get_launch": (ctypes.c_int, [_vp, _ip, _ip, _ip]),
     "lbm_batch_destroy": (ctypes.c_int, [_vp]),
 }
+
+
+class lbm_conv_shape(ctypes.Structure):
+    _fields_ = [("nb", ctypes.c_int), ("h", ctypes.c_int), ("w", ctypes.c_int),
+                ("cin", ctypes.c_int), ("cout", ctypes.c_int), ("cout_real", ctypes.c_int)]
+
+
+_cs = ctypes.POINTER(lbm_conv_shape)
+_sig.update({
+    "lbm_net_conv3x3_fwd": (ctypes.c_int, [_cs, _vp, ctypes.c_int, _vp, _vp, _vp, _vp]),
+    "lbm_net_conv3x3_bwd_data": (ctypes.c_int, [_cs, _vp, _vp, _vp, _vp, _vp]),
+    "lbm_net_conv3x3_bwd_weight_workspace": (ctypes.c_size_t, [_cs]),
+    "lbm_net_conv3x3_bwd_weight": (ctypes.c_int, [_cs, _vp, _vp, ctypes.c_int, _vp, _vp, _vp,
+                                                  ctypes.c_size_t, _vp]),
+    "lbm_net_mse": (ctypes.c_int, [ctypes.c_longlong, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp,
+                                   _vp, _dp, _vp]),
+    "lbm_net_adam": (ctypes.c_int, [ctypes.c_int, _vp, _vp, _vp, _vp, ctypes.c_double,
+                                    ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                    ctypes.c_longlong, _vp]),
+})
 BATCH_RUNNING, BATCH_CONVERGED, BATCH_MAXSTEPS, BATCH_DIVERGED, BATCH_NONFINITE = 0, 1, 2, 3, 4
 for _name, (_res, _args) in _sig.items():
     _f = getattr(_L, _name)
@@ -280,6 +300,44 @@ def lbm_batch_get_launch(bt):
 
 def lbm_batch_destroy(bt):
     _check(_L.lbm_batch_destroy(bt), "lbm_batch_destroy")
+
+
+def _shape(nb, h, w, cin, cout, cout_real=None):
+    return lbm_conv_shape(nb, h, w, cin, cout, cout if cout_real is None else cout_real)
+
+
+def lbm_net_conv3x3_fwd(shape, x, relu_in, w, b, out, stream=None):
+    _check(_L.lbm_net_conv3x3_fwd(ctypes.byref(shape), _ptr(x), int(relu_in), _ptr(w), _ptr(b),
+                                  _ptr(out), _stream(stream)), "lbm_net_conv3x3_fwd")
+
+
+def lbm_net_conv3x3_bwd_data(shape, dout, w, zin, din, stream=None):
+    _check(_L.lbm_net_conv3x3_bwd_data(ctypes.byref(shape), _ptr(dout), _ptr(w), _ptr(zin),
+                                       _ptr(din), _stream(stream)), "lbm_net_conv3x3_bwd_data")
+
+
+def lbm_net_conv3x3_bwd_weight_workspace(shape):
+    return int(_L.lbm_net_conv3x3_bwd_weight_workspace(ctypes.byref(shape)))
+
+
+def lbm_net_conv3x3_bwd_weight(shape, dout, x, relu_in, dw, db, ws, stream=None):
+    _check(_L.lbm_net_conv3x3_bwd_weight(ctypes.byref(shape), _ptr(dout), _ptr(x), int(relu_in),
+                                         _ptr(dw), _ptr(db), _ptr(ws),
+                                         ws.numel() * ws.element_size(), _stream(stream)),
+           "lbm_net_conv3x3_bwd_weight")
+
+
+def lbm_net_mse(npix, c, creal, pred, target, grad, part, want_loss=True, stream=None):
+    loss = ctypes.c_double()
+    _check(_L.lbm_net_mse(int(npix), int(c), int(creal), _ptr(pred), _ptr(target), _ptr(grad),
+                          _ptr(part), ctypes.byref(loss) if want_loss else None, _stream(stream)),
+           "lbm_net_mse")
+    return loss.value if want_loss else None
+
+
+def lbm_net_adam(p, g, m, v, lr, t, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    _check(_L.lbm_net_adam(p.numel(), _ptr(p), _ptr(g), _ptr(m), _ptr(v), float(lr), float(beta1),
+                           float(beta2), float(eps), int(t), _stream(stream)), "lbm_net_adam")
 
 
 # ---- convenience owners -----------------------------------------------------
