@@ -201,7 +201,7 @@ enum {
     LBM_BATCH_RUNNING = 0,
     LBM_BATCH_CONVERGED = 1,  /* residual <= tol                              */
     LBM_BATCH_MAXSTEPS = 2,   /* max_steps reached first                      */
-    LBM_BATCH_DIVERGED = 3,   /* residual rose at `patience` consecutive checks */
+    LBM_BATCH_DIVERGED = 3,   /* residual rose 10x above its minimum for `patience` checks */
     LBM_BATCH_NONFINITE = 4   /* non-finite state or b*rho >= 1              */
 };
 
@@ -224,8 +224,9 @@ int lbm_batch_step(lbm_batch *bt, long long nsteps);
  * Every K = check_every (rounded up to even) steps each active problem's
  * residual max_r |vel(r,t+1) - vel(r,t)| (vel as in lbm_moments, FP64) is
  * measured; the problem is retired as LBM_BATCH_CONVERGED when it is <= tol,
- * LBM_BATCH_DIVERGED when it rose at `patience` consecutive checks after
- * `grace` steps (patience <= 0 disables this), LBM_BATCH_NONFINITE on a bad
+ * LBM_BATCH_DIVERGED when, at `patience` consecutive checks after `grace`
+ * steps, it exceeded 10 times the smallest residual seen after `grace`
+ * (patience <= 0 disables this), LBM_BATCH_NONFINITE on a bad
  * state, LBM_BATCH_MAXSTEPS when its step count reaches max_steps.
  * Per-problem outputs (host, may be NULL): steps taken while active, last
  * residual, status.  Synchronises once per K steps (4 bytes read back). */

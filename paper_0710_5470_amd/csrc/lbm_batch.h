@@ -12,12 +12,19 @@ enum BatchStatus { BST_RUNNING = 0, BST_CONVERGED = 1, BST_MAXSTEPS = 2, BST_DIV
 struct BatchState {
     int active;        // 1 while the problem still steps
     int status;        // BatchStatus
-    int rises;         // consecutive checks with a rising residual
+    int rises;         // consecutive checks with a risen residual
     int pad;
     long long steps;   // steps taken while active
     double residual;   // last max |vel(t+1) - vel(t)|
     double max_vel;    // last max |vel|
+    double best;       // smallest residual seen after the grace period (0: none yet)
 };
+
+// A residual counts as risen when it exceeds the smallest one seen so far by
+// this factor: a decaying oscillation (sound waves crossing the box) makes
+// consecutive samples go up and down, a growing or stuck-high state does not
+// come back down.
+constexpr double RISE_FACTOR = 10.0;
 
 // One workgroup per problem: sum, min, max and bad-site count of a field
 // segment (initial density validation and the FP32 shift density).
@@ -82,14 +89,15 @@ __global__ __launch_bounds__(RED_THREADS) void batch_check_kernel(
         BatchState s = st[k];
         s.steps += steps_per_check;
         s.max_vel = v[0];
-        double prev_res = s.residual;
         s.residual = v[1];
         if (v[2] != 0.0) {
             s.status = BST_NONFINITE;
         } else if (v[1] <= tol) {
             s.status = BST_CONVERGED;
         } else {
-            s.rises = (s.steps > grace && prev_res > 0.0 && v[1] > prev_res) ? s.rises + 1 : 0;
+            const bool judged = s.steps > grace;
+            s.rises = (judged && s.best > 0.0 && v[1] > RISE_FACTOR * s.best) ? s.rises + 1 : 0;
+            if (judged && (s.best == 0.0 || v[1] < s.best)) s.best = v[1];
             if (patience > 0 && s.rises >= patience) s.status = BST_DIVERGED;
             else if (s.steps >= max_steps) s.status = BST_MAXSTEPS;
         }

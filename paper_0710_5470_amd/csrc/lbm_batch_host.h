@@ -24,6 +24,7 @@ struct lbm_batch {
     std::vector<long long> off, nsite;
     std::vector<int> gnx, gny, gnp; // kernel geometry per problem
     int tile, cp, nitems, grid;
+    int cus;                       // compute units of the device the batch runs on
     size_t o_a, o_b, o_rho, o_vel, o_prev, o_prob, o_coef, o_act, o_all, o_state, o_off, o_ns,
         o_b_coef, o_stats, o_count, total;
     hipGraphExec_t exec;
@@ -114,11 +115,14 @@ template <class L, int SCH, class S, class R, int TX, int TY>
 void batch_launch_one(lbm_batch *bt, const BatchArgs<R> &a)
 {
     auto kern = batch_step_kernel<L, SCH, S, R, TX, TY>;
-    int per_cu = 0, cus = 0, dev = 0;
-    hipGetDevice(&dev);
-    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, TX * TY, 0);
-    int g = std::max(1, per_cu) * std::max(1, cus);
+    // resident workgroups per CU of this instantiation (same on every gfx950)
+    static const int per_cu = [&] {
+        int v = 0;
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, kern, TX * TY, 0) == hipSuccess
+                   ? std::max(1, v)
+                   : 1;
+    }();
+    int g = per_cu * std::max(1, bt->cus);
     g = std::min(g, std::max(1, a.nitems));
     bt->grid = g;
     kern<<<g, TX * TY, 0, bt->stream>>>(a);
@@ -201,8 +205,8 @@ template <class L, class S> void batch_init_one(lbm_batch *bt, int k, const Coef
 int batch_capture(lbm_batch *bt, int K, double tol, int patience, long long grace, long long max_steps)
 {
     if (bt->graph_ok) {
-        hipGraphExecDestroy(bt->exec);
         bt->graph_ok = false;
+        if (hipGraphExecDestroy(bt->exec) != hipSuccess) return LBM_E_DEVICE;
     }
     hipGraph_t graph;
     if (hipStreamBeginCapture(bt->stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
@@ -224,8 +228,8 @@ int batch_capture(lbm_batch *bt, int K, double tol, int patience, long long grac
     hipError_t e = hipStreamEndCapture(bt->stream, &graph);
     if (e != hipSuccess) return LBM_E_DEVICE;
     e = hipGraphInstantiate(&bt->exec, graph, nullptr, nullptr, 0);
-    hipGraphDestroy(graph);
-    if (e != hipSuccess) return LBM_E_DEVICE;
+    const hipError_t ed = hipGraphDestroy(graph);
+    if (e != hipSuccess || ed != hipSuccess) return LBM_E_DEVICE;
     bt->graph_ok = true;
     bt->graph_K = K;
     return LBM_OK;
@@ -280,6 +284,15 @@ int lbm_batch_init(lbm_batch **out, int nprob, const lbm_params *pp, void *dev_w
     bt->graph_ok = false;
     bt->cur = 0;
     bt->steps = 0;
+    {
+        int dev = 0;
+        bt->cus = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&bt->cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+            delete bt;
+            return LBM_E_DEVICE;
+        }
+    }
     bt->tile = pp[0].tile >= 0 ? pp[0].tile : 0;
     bt->cp = pp[0].planes_per_block > 0 ? pp[0].planes_per_block : 16;
     std::vector<double> bcoef(nprob);
@@ -420,9 +433,9 @@ int lbm_batch_get_launch(const lbm_batch *bt, int *tile, int *planes, int *items
 int lbm_batch_destroy(lbm_batch *bt)
 {
     if (!bt) return LBM_E_INVAL;
-    if (bt->graph_ok) hipGraphExecDestroy(bt->exec);
+    const hipError_t e = bt->graph_ok ? hipGraphExecDestroy(bt->exec) : hipSuccess;
     delete bt;
-    return LBM_OK;
+    return e == hipSuccess ? LBM_OK : LBM_E_DEVICE;
 }
 
 } // extern "C"

@@ -18,10 +18,10 @@
 // neighbouring tiles (they come from L2 / MALL when the neighbours run
 // concurrently, which the XCD-aware workgroup order encourages).
 //
-// Population arrays are read and written through buffer resources (one per
-// direction, 32-bit byte offsets, hardware range check), with all wrapped
-// neighbour offsets precomputed per thread, so the per-load address work is
-// two integer adds.
+// Population arrays are read and written through one buffer resource per
+// array (32-bit byte offsets, hardware range check); the direction's offset
+// rides in the scalar offset and the wrapped neighbour offsets are
+// precomputed per thread, so a load needs no per-direction address work.
 #pragma once
 
 #include <type_traits>
@@ -116,7 +116,6 @@ __device__ __forceinline__ void step_tile(const Job<R> &J, const Coefs<R> &c)
     S *dst = static_cast<S *>(J.dst);
     const long long stride = J.stride;
     const int nx = J.nx, ny = J.ny, np = J.np;
-    const int n = J.n;
     const int psz = nx * ny;  // elements per plane
     const int x0 = J.x0, y0 = J.y0, p0 = J.p0, npl = J.npl;
     const __amdgpu_buffer_rsrc_t rs = pop_rsrc(src, J.bytes);

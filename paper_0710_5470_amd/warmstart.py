@@ -2,10 +2,12 @@
 
 A small periodic convolutional network (6 layers, 3x3 kernels, 32 channels,
 relu) maps the drop parameters (a, b, T, kappa, R as constant planes) and the
-initial density to a near-steady (rho, u_x, u_y) field.  The batched lattice
-Boltzmann runner then starts from the equilibrium of that field, judges
-convergence by its own residual and falls back to a cold start for any
-problem whose residual keeps rising.
+initial density to a near-steady (rho, u_x, u_y) field.  The prediction is
+averaged over the square's eight symmetries (the centred drop's steady state
+has them) and given the cold start's mass and zero momentum.  The batched
+lattice Boltzmann runner then starts from the equilibrium of that field,
+judges convergence by its own residual and falls back to a cold start for
+any problem whose residual rises tenfold above its best.
 
 Every arithmetic step of the network runs in this library's HIP kernels
 (bf16 matrix cores, FP32 accumulation; see the lbm_net_* entry points);
@@ -28,7 +30,7 @@ CP_IN, CP_OUT = 16, 16
 
 # feature / target scales (fixed, so a trained net can be reused)
 SCALE = dict(T=(0.55, 0.01), kappa=(0.0125, 0.005), R=(0.25, 0.06), rho=(3.5, 1.0),
-             drho=0.05, u=1e-4)
+             drho=0.2, u=1e-3)
 
 
 def features(specs, side, rho0):
@@ -200,8 +202,26 @@ def mass_momentum_projection(rho_pred, u_pred, rho0):
     return rho, u
 
 
+def d4_symmetrize(rho, u):
+    """Average (rho [n, Y, X], u [n, 2, Y, X]) over the 8 symmetries of a
+    square about the node (Y/2, X/2): the centred drop and its steady state
+    are invariant under them, so this removes prediction errors that would
+    seed the slow, symmetry-breaking shear modes of the periodic box."""
+    fx = lambda a: np.roll(a[..., :, ::-1], 1, axis=-1)
+    fy = lambda a: np.roll(a[..., ::-1, :], 1, axis=-2)
+    tr = lambda a: np.swapaxes(a, -1, -2)
+    ux, uy = u[:, 0], u[:, 1]
+    imgs = [(rho, ux, uy), (fx(rho), -fx(ux), fx(uy)), (fy(rho), fy(ux), -fy(uy)),
+            (fx(fy(rho)), -fx(fy(ux)), -fx(fy(uy)))]
+    imgs += [(tr(r), tr(b), tr(a)) for r, a, b in imgs]
+    r = sum(i[0] for i in imgs) / 8.0
+    vx = sum(i[1] for i in imgs) / 8.0
+    vy = sum(i[2] for i in imgs) / 8.0
+    return r, np.stack([vx, vy], axis=1)
+
+
 def warm_start(net, specs, side, tol=1e-10, check_every=100, max_steps=60000, patience=3,
-               grace=500):
+               grace=500, symmetrize=True, with_velocity=True):
     """Predict, project, run with the rising-residual check; problems that
     diverge are rerun from the cold start.  Returns per-problem total steps,
     statuses, the fallback mask and wall seconds (inference included)."""
@@ -211,6 +231,14 @@ def warm_start(net, specs, side, tol=1e-10, check_every=100, max_steps=60000, pa
     x = torch.tensor(features(specs, side, rho0), device=net.dev)
     pred = net.predict(x).cpu().numpy()
     rho_p, u_p = decode(pred, rho0)
+    # a non-finite prediction falls back to the cold initial field at once
+    bad = ~(np.isfinite(rho_p).all(axis=(1, 2)) & np.isfinite(u_p).all(axis=(1, 2, 3)))
+    rho_p[bad] = rho0[bad]
+    u_p[bad] = 0.0
+    if not with_velocity:
+        u_p[:] = 0.0
+    if symmetrize:
+        rho_p, u_p = d4_symmetrize(rho_p, u_p)
     rho_p, u_p = mass_momentum_projection(rho_p, u_p, rho0)
     t_inf = time.perf_counter() - t0
     rho, vel, steps, res, status, secs = steady_states(specs, side, tol, check_every, max_steps,
@@ -228,3 +256,111 @@ def warm_start(net, specs, side, tol=1e-10, check_every=100, max_steps=60000, pa
         status[idx] = st2
     return dict(steps=total, status=status, fallback=fallback, seconds=t_inf + secs + secs_fb,
                 inference_seconds=t_inf, rho=rho, vel=vel)
+
+
+# ---- end-to-end experiment: generate, train, compare warm vs cold ----------
+
+def _log(*a):
+    print("[warmstart]", *a, flush=True)
+
+
+def generate(nprob, side, seed, batch=512, tol=1e-10, max_steps=60000):
+    """Steady states of `nprob` drops from the stable batched workload
+    (side fixed), by the batched runner.  Returns (specs, x, y, steps)."""
+    specs = inputs.stable_batch_specs(nprob, seed, side_lo=side, side_hi=side)
+    xs, ys, steps, kept = [], [], [], []
+    for i in range(0, nprob, batch):
+        sub = specs[i:i + batch]
+        rho, vel, st, res, status, secs = steady_states(sub, side, tol, 100, max_steps)
+        _, rho0 = problems(sub, side)
+        ok = status == lbm.BATCH_CONVERGED
+        xs.append(features(sub, side, rho0)[ok])
+        ys.append(targets(rho0, rho, vel)[ok])
+        steps.append(st[ok])
+        kept += [s for s, o in zip(sub, ok) if o]
+        _log("generated %d/%d steady states (%.1f s, median steps %d, status counts %s)"
+             % (i + len(sub), nprob, secs, int(np.median(st)), np.bincount(status, minlength=5).tolist()))
+    return kept, np.concatenate(xs), np.concatenate(ys), np.concatenate(steps)
+
+
+def train(net, x, y, epochs, batch=16, lr=1e-3, seed=1):
+    """Plain minibatch Adam; x, y device tensors.  Returns per-epoch losses."""
+    n = x.shape[0]
+    st = inputs.Stream(seed)
+    losses = []
+    for ep in range(epochs):
+        lr_ep = lr * 0.5 * (1.0 + math.cos(math.pi * ep / epochs))  # cosine decay
+        order = np.argsort(st.uniform(n))
+        tot = 0.0
+        for i in range(0, n - batch + 1, batch):
+            idx = torch.tensor(order[i:i + batch], device=net.dev)
+            tot += net.train_step(x.index_select(0, idx).contiguous(),
+                                  y.index_select(0, idx).contiguous(), lr_ep) * batch
+        losses.append(tot / (n - n % batch))
+        _log("epoch %d loss %.5f lr %.1e" % (ep, losses[-1], lr_ep))
+    return losses
+
+
+def run_experiment(n_train=2048, n_eval=512, side=128, epochs=20, seed_train=5, seed_eval=6,
+                   tol=1e-10, out_json=None, weights=None):
+    t0 = time.perf_counter()
+    _, xtr, ytr, _ = generate(n_train, side, seed_train, tol=tol)
+    t_gen = time.perf_counter() - t0
+    net = WarmNet(seed=7)
+    dev = net.dev
+    xt, yt = torch.tensor(xtr, device=dev), torch.tensor(ytr, device=dev)
+    t1 = time.perf_counter()
+    losses = train(net, xt, yt, epochs)
+    t_train = time.perf_counter() - t1
+    del xt, yt
+    specs = inputs.stable_batch_specs(n_eval, seed_eval, side_lo=side, side_hi=side)
+    cold_rho, _, cold_steps, cold_res, cold_status, cold_secs = steady_states(specs, side, tol)
+    _log("cold: %.2f s, median steps %d" % (cold_secs, int(np.median(cold_steps))))
+    variants = {}
+    for name, kw in (("raw", dict(symmetrize=False)), ("sym_rho_only", dict(with_velocity=False)),
+                     ("sym", dict())):
+        w = warm_start(net, specs, side, tol, **kw)
+        _log("warm[%s]: %.2f s, median steps %d, fallbacks %d"
+             % (name, w["seconds"], int(np.median(w["steps"])), int(w["fallback"].sum())))
+        ok = (w["status"] == lbm.BATCH_CONVERGED) & (cold_status == lbm.BATCH_CONVERGED) & ~w["fallback"]
+        diff = float(np.max(np.abs(w["rho"][ok] - cold_rho[ok]) / cold_rho[ok])) if ok.any() else None
+        variants[name] = dict(seconds=w["seconds"], steps_median=float(np.median(w["steps"])),
+                              steps_total=int(w["steps"].sum()), fallbacks=int(w["fallback"].sum()),
+                              rho_rel_diff_vs_cold=diff)
+    warm = w
+    ratio = warm["steps"] / np.maximum(cold_steps, 1)
+    res = dict(n_train=n_train, n_eval=n_eval, side=side, epochs=epochs, tol=tol,
+               seconds_generate=t_gen, seconds_train=t_train, final_loss=losses[-1], losses=losses,
+               cold_seconds=cold_secs, warm_seconds=warm["seconds"],
+               warm_inference_seconds=warm["inference_seconds"],
+               cold_steps_median=float(np.median(cold_steps)), warm_steps_median=float(np.median(warm["steps"])),
+               cold_steps_total=int(cold_steps.sum()), warm_steps_total=int(warm["steps"].sum()),
+               step_ratio_median=float(np.median(ratio)), step_ratio_p10=float(np.percentile(ratio, 10)),
+               step_ratio_p90=float(np.percentile(ratio, 90)),
+               cold_converged=int((cold_status == lbm.BATCH_CONVERGED).sum()),
+               warm_converged=int((warm["status"] == lbm.BATCH_CONVERGED).sum()),
+               fallbacks=int(warm["fallback"].sum()), variants=variants,
+               zero_prediction_loss=float((ytr[..., :OUT_REAL].astype(np.float64) ** 2).mean()))
+    if out_json:
+        import json
+        with open(out_json, "w") as fh:
+            json.dump(res, fh, indent=1)
+    if weights:
+        np.savez(weights, *[a for W, b in net.numpy_params() for a in (W, b)])
+    return res, net
+
+
+if __name__ == "__main__":
+    import argparse
+    import json
+    ap = argparse.ArgumentParser(description="learned warm start: generate, train, compare")
+    ap.add_argument("--train", type=int, default=2048)
+    ap.add_argument("--eval", type=int, default=512)
+    ap.add_argument("--side", type=int, default=128)
+    ap.add_argument("--epochs", type=int, default=20)
+    ap.add_argument("--tol", type=float, default=1e-10)
+    ap.add_argument("--out", default=None)
+    ap.add_argument("--weights", default=None)
+    a = ap.parse_args()
+    r, _ = run_experiment(a.train, a.eval, a.side, a.epochs, tol=a.tol, out_json=a.out, weights=a.weights)
+    print(json.dumps({k: v for k, v in r.items() if k != "losses"}))

@@ -89,8 +89,9 @@ def test_batch_runs_to_residual_and_retires_problems():
 
 
 def test_batch_detects_rising_residual():
-    """With patience 1 and no grace period, a problem whose residual rises
-    between two checks is retired as diverged."""
+    """With patience 1 and no grace period, a problem whose residual grows
+    tenfold above its smallest value (an unstable liquid at T = 0.5) is
+    retired as diverged, or as non-finite if it blows up between checks."""
     from paper_0710_5470_amd import lbm
     plist, rho = _problems([dict(side=48, radius=10.0, T=0.5, kappa=0.02)], 0, 0)
     bt = lbm.Batch(plist, rho)
