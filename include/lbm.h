@@ -300,6 +300,36 @@ int lbm_net_mse(long long npix, int c, int creal, const float *dev_pred, const f
 int lbm_net_adam(int n, float *dev_param, const float *dev_grad, float *dev_m, float *dev_v,
                  double lr, double beta1, double beta2, double eps, long long t, void *stream);
 
+/* ---- warm-start data preparation ----------------------------------------
+ *
+ * For nprob square side x side D2Q9 problems stored back to back (site
+ * s = y side + x of problem k at k side^2 + s), each a drop centred on the
+ * node (side/2, side/2).  Only enqueue on `stream`. */
+
+/* Network input [nprob][side][side][16] FP32 (16-byte aligned): channels
+ * 0..4 = dev_consts[k][0..4] (per-problem normalised constants: a, b, T,
+ * kappa, R / side), channel 5 = (rho0 - rho_mean) / rho_scale, others 0. */
+int lbm_warm_features(int nprob, int side, const double *dev_consts, const double *dev_rho0, double rho_mean,
+                      double rho_scale, float *dev_x, void *stream);
+
+/* Training target [ntot][16] FP32 (16-byte aligned) from a steady state:
+ * channel 0 = (rho - rho0) / s_rho, channels 1, 2 = (u_x, u_y) / s_u with
+ * dev_vel [3][ntot], others 0. */
+int lbm_warm_targets(long long ntot, const double *dev_rho, const double *dev_rho0, const double *dev_vel,
+                     double s_rho, double s_u, float *dev_y, void *stream);
+
+/* Initial field from a network prediction pred [nprob][side][side][cpad]
+ * (channel 0 = (rho - rho0) / s_rho, channels 1, 2 = u / s_u): decode; if
+ * symmetrize, average over the eight symmetries of the square about the
+ * centre (scalar rho(g p), vector M_g^T u(g p)); add the uniform density that
+ * gives the cold start's mass; clamp rho to [rho_lo, rho_hi]; subtract the
+ * mass-weighted mean velocity.  with_velocity = 0 starts from u = 0.  A
+ * problem with a non-finite prediction gets rho0 and u = 0.  Outputs FP64:
+ * dev_rho [nprob side^2], dev_u [3][nprob side^2] (z component 0). */
+int lbm_warm_project(int nprob, int side, int cpad, const float *dev_pred, const double *dev_rho0, double s_rho,
+                     double s_u, int with_velocity, int symmetrize, double rho_lo, double rho_hi, double *dev_rho,
+                     double *dev_u, void *stream);
+
 /* Human-readable name of a status code. */
 const char *lbm_strerror(int code);
 

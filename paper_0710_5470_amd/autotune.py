@@ -6,6 +6,7 @@ Results never depend on the launch shape (every shape runs the same
 per-site arithmetic), so tuning only changes speed.  The best choice per
 (lattice, scheme, storage, compute, extent, device) is cached in a JSON file.
 """
+import hashlib
 import json
 import sys
 import os
@@ -82,3 +83,63 @@ def autotune(sim, steps=10, use_cache=True, verbose=False):
         except OSError:
             pass
     return dict(best, cached=False, table=[(t_, c_, m_) for m_, t_, c_ in results])
+
+
+def _batch_key(plist):
+    p = plist[0]
+    dev = torch.cuda.get_device_name() if torch.cuda.is_available() else "none"
+    sizes = sorted((q.nx, q.ny, q.nz) for q in plist)
+    sig = "%d:%s" % (len(sizes), hashlib.sha1(repr(sizes).encode()).hexdigest()[:12])
+    return "%s|batch|q%d|s%d|st%d|c%d|%s" % (dev, p.lattice, p.scheme, p.storage, p.compute, sig)
+
+
+def batch_candidates(plist):
+    p = plist[0]
+    np_max = max(q.nz if q.lattice == lbm.D3Q19 else q.ny for q in plist)
+    planes = sorted(set(min(c, np_max) for c in (8, 16, 32, 64)))
+    return [(t, c) for t in range(lbm.lbm_tile_count(p.lattice)) for c in planes]
+
+
+def autotune_batch(plist, rho0, steps=8, use_cache=True, verbose=False):
+    """Pick the fastest (tile, planes per work item) for a batch of
+    problems by timing a throwaway copy of the batch (the caller's batch
+    keeps its state and step counts).  Returns (tile, planes)."""
+    key = _batch_key(plist)
+    cache = {}
+    if use_cache and os.path.exists(CACHE):
+        try:
+            with open(CACHE) as fh:
+                cache = json.load(fh)
+        except (OSError, ValueError):
+            cache = {}
+    if use_cache and key in cache:
+        return cache[key]["tile"], cache[key]["planes"]
+    bt = lbm.Batch(plist, rho0)
+    results = []
+    try:
+        for t, c in batch_candidates(plist):
+            bt.set_launch(t, c)
+            bt.step(2)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(bt.stream)
+            bt.step(steps)
+            e1.record(bt.stream)
+            e1.synchronize()
+            ms = e0.elapsed_time(e1) / steps
+            results.append((ms, t, c))
+            if verbose:
+                print("autotune batch tile %d planes %d: %.4f ms/step" % (t, c, ms), file=sys.stderr,
+                      flush=True)
+    finally:
+        bt.close()
+    ms, t, c = min(results)
+    if use_cache:
+        cache[key] = dict(tile=t, planes=c, ms=ms)
+        try:
+            os.makedirs(os.path.dirname(CACHE), exist_ok=True)
+            with open(CACHE, "w") as fh:
+                json.dump(cache, fh, indent=1)
+        except OSError:
+            pass
+    return t, c

@@ -141,7 +141,8 @@ template <class L, int SCH, class S, class R> void batch_launch_tiles(lbm_batch 
         case 0: batch_launch_one<L, SCH, S, R, 64, 4>(bt, a); break;
         case 1: batch_launch_one<L, SCH, S, R, 32, 8>(bt, a); break;
         case 2: batch_launch_one<L, SCH, S, R, 64, 8>(bt, a); break;
-        default: batch_launch_one<L, SCH, S, R, 32, 16>(bt, a); break;
+        case 3: batch_launch_one<L, SCH, S, R, 32, 16>(bt, a); break;
+        default: batch_launch_one<L, SCH, S, R, 128, 4>(bt, a); break;
         }
     }
 }

@@ -30,7 +30,7 @@ struct TileShape {
 };
 // D2Q9 marches along y with a row of tx sites; D3Q19 marches along z.
 constexpr TileShape TILES_2D[] = {{64, 1}, {128, 1}, {256, 1}};
-constexpr TileShape TILES_3D[] = {{64, 4}, {32, 8}, {64, 8}, {32, 16}};
+constexpr TileShape TILES_3D[] = {{64, 4}, {32, 8}, {64, 8}, {32, 16}, {128, 4}};
 constexpr int NT2 = sizeof(TILES_2D) / sizeof(TILES_2D[0]);
 constexpr int NT3 = sizeof(TILES_3D) / sizeof(TILES_3D[0]);
 
@@ -274,7 +274,8 @@ void launch_tiles(lbm_ctx *c, const StepArgs<R> &a)
         case 0: launch_one<L, SCH, S, R, 64, 4>(c, a); break;
         case 1: launch_one<L, SCH, S, R, 32, 8>(c, a); break;
         case 2: launch_one<L, SCH, S, R, 64, 8>(c, a); break;
-        default: launch_one<L, SCH, S, R, 32, 16>(c, a); break;
+        case 3: launch_one<L, SCH, S, R, 32, 16>(c, a); break;
+        default: launch_one<L, SCH, S, R, 128, 4>(c, a); break;
         }
     }
 }

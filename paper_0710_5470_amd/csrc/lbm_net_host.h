@@ -2,6 +2,7 @@
 // once, at the end of lbm_capi.hip).
 
 #include "lbm_net.h"
+#include "lbm_warm.h"
 
 namespace {
 
@@ -107,6 +108,43 @@ int lbm_net_adam(int n, float *dev_p, const float *dev_g, float *dev_m, float *d
     double c1 = 1.0 - std::pow(b1, double(t)), c2 = 1.0 - std::pow(b2, double(t));
     lbmnet::adam_kernel<<<(n + 255) / 256, 256, 0, static_cast<hipStream_t>(stream)>>>(
         n, dev_p, dev_g, dev_m, dev_v, float(lr), float(b1), float(b2), float(eps), float(c1), float(c2));
+    return hipGetLastError() == hipSuccess ? LBM_OK : LBM_E_DEVICE;
+}
+
+int lbm_warm_features(int nprob, int side, const double *dev_consts, const double *dev_rho0, double rho_mean,
+                      double rho_scale, float *dev_x, void *stream)
+{
+    if (nprob < 1 || side < 1 || !dev_consts || !dev_rho0 || !aligned16(dev_x) || !(rho_scale != 0.0))
+        return LBM_E_INVAL;
+    const long long total = (long long)nprob * side * side;
+    const unsigned grid = unsigned(std::min<long long>((total + 255) / 256, 65536));
+    lbmwarm::warm_features_kernel<<<grid, 256, 0, static_cast<hipStream_t>(stream)>>>(
+        nprob, side, dev_consts, dev_rho0, rho_mean, rho_scale, dev_x);
+    return hipGetLastError() == hipSuccess ? LBM_OK : LBM_E_DEVICE;
+}
+
+int lbm_warm_targets(long long ntot, const double *dev_rho, const double *dev_rho0, const double *dev_vel,
+                     double s_rho, double s_u, float *dev_y, void *stream)
+{
+    if (ntot < 1 || !dev_rho || !dev_rho0 || !dev_vel || !aligned16(dev_y) || !(s_rho != 0.0) || !(s_u != 0.0))
+        return LBM_E_INVAL;
+    const unsigned grid = unsigned(std::min<long long>((ntot + 255) / 256, 65536));
+    lbmwarm::warm_targets_kernel<<<grid, 256, 0, static_cast<hipStream_t>(stream)>>>(ntot, dev_rho, dev_rho0,
+                                                                                    dev_vel, s_rho, s_u, dev_y);
+    return hipGetLastError() == hipSuccess ? LBM_OK : LBM_E_DEVICE;
+}
+
+int lbm_warm_project(int nprob, int side, int cpad, const float *dev_pred, const double *dev_rho0, double s_rho,
+                     double s_u, int with_velocity, int symmetrize, double rho_lo, double rho_hi, double *dev_rho,
+                     double *dev_u, void *stream)
+{
+    if (nprob < 1 || side < 1 || cpad < (with_velocity ? 3 : 1) || !dev_pred || !dev_rho0 || !dev_rho ||
+        !dev_u || !(rho_lo < rho_hi))
+        return LBM_E_INVAL;
+    const long long ntot = (long long)nprob * side * side;
+    lbmwarm::warm_project_kernel<<<nprob, lbmwarm::WARM_THREADS, 0, static_cast<hipStream_t>(stream)>>>(
+        side, cpad, dev_pred, dev_rho0, s_rho, s_u, with_velocity, symmetrize, rho_lo, rho_hi, dev_rho, dev_u,
+        ntot);
     return hipGetLastError() == hipSuccess ? LBM_OK : LBM_E_DEVICE;
 }
 

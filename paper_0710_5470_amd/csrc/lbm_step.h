@@ -60,15 +60,22 @@ __device__ __forceinline__ double buf_load(__amdgpu_buffer_rsrc_t r, unsigned vo
 {
     return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
 }
+// Cache policy of the population stores (0: default).  The stored state is
+// read again only in the next step, long after it has left the caches.
+#ifndef LBM_STORE_CPOL
+#define LBM_STORE_CPOL 0
+#endif
+
 __device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, float v)
 {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)voff, (int)soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)voff, (int)soff,
+                                          LBM_STORE_CPOL);
 }
 __device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, double v)
 {
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(decltype(__builtin_amdgcn_raw_buffer_load_b64(
                                               r, 0, 0, 0)), v),
-                                          r, (int)voff, (int)soff, 0);
+                                          r, (int)voff, (int)soff, LBM_STORE_CPOL);
 }
 
 #ifndef LBM_STEP_WAVES_PER_EU
@@ -266,12 +273,12 @@ __device__ __forceinline__ void step_tile(const Job<R> &J, const Coefs<R> &c)
     // lives in fr[k mod (H + 2)], so the loop below is unrolled H + 2 times
     // and no registers move between planes (moves of in-flight load targets
     // would force waits at the loop head).
-    auto iteration = [&](const int k, auto phase) {
+    auto iteration = [&](const int k, auto phase, auto always_more) {
         constexpr int RING = H + 2;
         constexpr int C0 = decltype(phase)::value % RING;            // plane lc
         constexpr int CN = (decltype(phase)::value + H + 1) % RING;  // plane lc + H + 1
         const int lc = H + k;  // local index of the plane collided now
-        const bool more = k + 1 < npl;
+        const bool more = decltype(always_more)::value || k + 1 < npl;
         if (more) load_plane(lc + H + 1, fr[CN]);  // consumed after the collision
         __syncthreads();  // densities up to plane lc + H are in LDS
         if (FORCE) {
@@ -363,13 +370,27 @@ __device__ __forceinline__ void step_tile(const Job<R> &J, const Coefs<R> &c)
         }
     };
 
-    for (int k = 0; k < npl; k += H + 2) {
-        iteration(k, std::integral_constant<int, 0>{});
-        if (k + 1 < npl) iteration(k + 1, std::integral_constant<int, 1>{});
-        if (k + 2 < npl) iteration(k + 2, std::integral_constant<int, 2>{});
-        if constexpr (H == 2) {
-            if (k + 3 < npl) iteration(k + 3, std::integral_constant<int, 3>{});
-        }
+    // Full groups of H + 2 planes, every one of which prefetches: the loads
+    // and the waits for them are unconditional here, so the compiler's wait
+    // counting knows that the register ring is complete at the loop head (a
+    // runtime prefetch condition made it wait for the fresh loads before the
+    // collision).  The last group checks the condition at run time.
+    using P0 = std::integral_constant<int, 0>;
+    using P1 = std::integral_constant<int, 1>;
+    using P2 = std::integral_constant<int, 2>;
+    using P3 = std::integral_constant<int, 3>;
+    int k = 0;
+    for (; k + H + 2 < npl; k += H + 2) {
+        iteration(k, P0{}, std::true_type{});
+        iteration(k + 1, P1{}, std::true_type{});
+        iteration(k + 2, P2{}, std::true_type{});
+        if constexpr (H == 2) iteration(k + 3, P3{}, std::true_type{});
+    }
+    iteration(k, P0{}, std::false_type{});
+    if (k + 1 < npl) iteration(k + 1, P1{}, std::false_type{});
+    if (k + 2 < npl) iteration(k + 2, P2{}, std::false_type{});
+    if constexpr (H == 2) {
+        if (k + 3 < npl) iteration(k + 3, P3{}, std::false_type{});
     }
 }
 

@@ -105,6 +105,13 @@ _sig.update({
     "lbm_net_adam": (ctypes.c_int, [ctypes.c_int, _vp, _vp, _vp, _vp, ctypes.c_double,
                                     ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                     ctypes.c_longlong, _vp]),
+    "lbm_warm_features": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _vp, _vp, ctypes.c_double,
+                                         ctypes.c_double, _vp, _vp]),
+    "lbm_warm_targets": (ctypes.c_int, [ctypes.c_longlong, _vp, _vp, _vp, ctypes.c_double,
+                                        ctypes.c_double, _vp, _vp]),
+    "lbm_warm_project": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp, _vp,
+                                        ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                                        ctypes.c_double, ctypes.c_double, _vp, _vp, _vp]),
 })
 BATCH_RUNNING, BATCH_CONVERGED, BATCH_MAXSTEPS, BATCH_DIVERGED, BATCH_NONFINITE = 0, 1, 2, 3, 4
 for _name, (_res, _args) in _sig.items():
@@ -338,6 +345,24 @@ def lbm_net_mse(npix, c, creal, pred, target, grad, part, want_loss=True, stream
 def lbm_net_adam(p, g, m, v, lr, t, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
     _check(_L.lbm_net_adam(p.numel(), _ptr(p), _ptr(g), _ptr(m), _ptr(v), float(lr), float(beta1),
                            float(beta2), float(eps), int(t), _stream(stream)), "lbm_net_adam")
+
+
+def lbm_warm_features(nprob, side, consts, rho0, rho_mean, rho_scale, x, stream=None):
+    _check(_L.lbm_warm_features(int(nprob), int(side), _ptr(consts), _ptr(rho0), float(rho_mean),
+                                float(rho_scale), _ptr(x), _stream(stream)), "lbm_warm_features")
+
+
+def lbm_warm_targets(rho, rho0, vel, s_rho, s_u, y, stream=None):
+    _check(_L.lbm_warm_targets(int(rho.numel()), _ptr(rho), _ptr(rho0), _ptr(vel), float(s_rho),
+                               float(s_u), _ptr(y), _stream(stream)), "lbm_warm_targets")
+
+
+def lbm_warm_project(nprob, side, cpad, pred, rho0, s_rho, s_u, with_velocity, symmetrize, rho_lo,
+                     rho_hi, rho, u, stream=None):
+    _check(_L.lbm_warm_project(int(nprob), int(side), int(cpad), _ptr(pred), _ptr(rho0), float(s_rho),
+                               float(s_u), int(bool(with_velocity)), int(bool(symmetrize)),
+                               float(rho_lo), float(rho_hi), _ptr(rho), _ptr(u), _stream(stream)),
+           "lbm_warm_project")
 
 
 # ---- convenience owners -----------------------------------------------------

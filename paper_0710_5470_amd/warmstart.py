@@ -20,7 +20,7 @@ import time
 import numpy as np
 import torch
 
-from . import inputs, lbm
+from . import autotune, inputs, lbm
 
 A_VDW, B_VDW = 9.0 / 49.0, 2.0 / 21.0
 # (padded cin, padded cout, real cout) per layer; 6 real input channels
@@ -33,35 +33,36 @@ SCALE = dict(T=(0.55, 0.01), kappa=(0.0125, 0.005), R=(0.25, 0.06), rho=(3.5, 1.
              drho=0.2, u=1e-3)
 
 
-def features(specs, side, rho0):
-    """[n, side, side, 16] FP32 network input: a, b (constant, so zero after
-    centring), T, kappa, R / side as normalised constant planes, and the
-    normalised initial density."""
-    n = len(specs)
-    x = np.zeros((n, side, side, CP_IN), dtype=np.float32)
+RHO_LO = 1e-3            # clamp of the projected density (the vdW bound is 1/b)
+
+
+def _consts(specs, side):
+    """Per-problem normalised constants [n, 5]: a, b (the same for every
+    problem, so zero after centring), T, kappa, R / side."""
+    c = np.zeros((len(specs), 5))
     for k, s in enumerate(specs):
-        x[k, :, :, 2] = (s["T"] - SCALE["T"][0]) / SCALE["T"][1]
-        x[k, :, :, 3] = (s["kappa"] - SCALE["kappa"][0]) / SCALE["kappa"][1]
-        x[k, :, :, 4] = (s["radius"] / side - SCALE["R"][0]) / SCALE["R"][1]
-        x[k, :, :, 5] = (rho0[k] - SCALE["rho"][0]) / SCALE["rho"][1]
+        c[k, 2] = (s["T"] - SCALE["T"][0]) / SCALE["T"][1]
+        c[k, 3] = (s["kappa"] - SCALE["kappa"][0]) / SCALE["kappa"][1]
+        c[k, 4] = (s["radius"] / side - SCALE["R"][0]) / SCALE["R"][1]
+    return c
+
+
+def features(specs, side, rho0, device="cuda"):
+    """[n, side, side, 16] FP32 network input on the device (channels:
+    the constants of `_consts`, then the normalised initial density)."""
+    n = len(specs)
+    consts = torch.tensor(_consts(specs, side), dtype=torch.float64, device=device)
+    x = torch.empty(n, side, side, CP_IN, dtype=torch.float32, device=device)
+    lbm.lbm_warm_features(n, side, consts, rho0, SCALE["rho"][0], SCALE["rho"][1], x)
     return x
 
 
-def targets(rho0, rho, vel):
+def targets(rho, rho0, vel, side):
     """[n, side, side, 16]: (rho - rho0) / s_rho, u_x / s_u, u_y / s_u."""
-    n, side = rho.shape[0], rho.shape[1]
-    y = np.zeros((n, side, side, CP_OUT), dtype=np.float32)
-    y[..., 0] = (rho - rho0) / SCALE["drho"]
-    y[..., 1] = vel[:, 0] / SCALE["u"]
-    y[..., 2] = vel[:, 1] / SCALE["u"]
+    n = rho.numel() // (side * side)
+    y = torch.empty(n, side, side, CP_OUT, dtype=torch.float32, device=rho.device)
+    lbm.lbm_warm_targets(rho, rho0, vel, SCALE["drho"], SCALE["u"], y)
     return y
-
-
-def decode(pred, rho0):
-    """Network output -> (rho, u) fields, numpy FP64."""
-    rho = rho0 + SCALE["drho"] * pred[..., 0].astype(np.float64)
-    u = np.stack([SCALE["u"] * pred[..., 1], SCALE["u"] * pred[..., 2]], axis=1).astype(np.float64)
-    return rho, u
 
 
 class WarmNet:
@@ -154,108 +155,77 @@ class WarmNet:
 
 # ---- data from the lattice Boltzmann runner --------------------------------
 
-def problems(specs, side, storage=lbm.STORE_F64, tau=1.0):
+def problems(specs, side, storage=lbm.STORE_F64, tau=1.0, device="cuda"):
+    """Lattice parameters and the cold initial densities (tanh drop between
+    the Maxwell densities), concatenated on the device as [n side^2]."""
     plist, rho0 = [], []
     for s in specs:
         g, l = lbm.lbm_coexistence(A_VDW, B_VDW, s["T"])
         plist.append(lbm.params(lattice=lbm.D2Q9, scheme=lbm.SCHEME_EQ, storage=storage,
                                 shape=(side, side), T=s["T"], kappa=s["kappa"], tau=tau))
-        rho0.append(inputs.tanh_drop((side, side), s["radius"], l, g, 2.0))
-    return plist, np.stack(rho0)
+        rho0.append(inputs.tanh_drop((side, side), s["radius"], l, g, 2.0).reshape(-1))
+    return plist, torch.tensor(np.concatenate(rho0), dtype=torch.float64, device=device)
 
 
 def steady_states(specs, side, tol=1e-10, check_every=100, max_steps=60000, rho_init=None,
-                  u_init=None, patience=0, grace=0):
-    """Run a batch to its residual; returns (rho, vel [n,2,side,side], steps,
-    residual, status, seconds)."""
+                  u_init=None, patience=0, grace=0, tune=True, settle_tol=None, settle_steps=120000):
+    """Run a batch (cold, or from rho_init [n side^2] / u_init [3, n side^2]
+    device fields) to its residual.  Returns a dict with device fields rho
+    [n side^2], vel [3, n side^2], host arrays steps, residual, status and the
+    wall seconds from batch creation to the last check.  With settle_tol, the
+    same batch then continues (untimed) to that tighter residual and
+    rho_settled holds the density it reaches."""
     plist, rho0 = problems(specs, side)
-    r_in = rho0 if rho_init is None else rho_init
-    u_in = None
-    if u_init is not None:
-        u_in = np.zeros((3,) + (len(specs) * side * side,))
-        u_in[0] = np.concatenate([u_init[k, 0].reshape(-1) for k in range(len(specs))])
-        u_in[1] = np.concatenate([u_init[k, 1].reshape(-1) for k in range(len(specs))])
+    launch = autotune.autotune_batch(plist, rho0) if tune else None
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    bt = lbm.Batch(plist, list(r_in), u_in)
+    bt = lbm.Batch(plist, rho0 if rho_init is None else rho_init, u_init)
+    if launch is not None:
+        bt.set_launch(*launch)
     steps, res, status = bt.run(tol, check_every, max_steps, patience, grace)
     secs = time.perf_counter() - t0
     rho, vel = bt.moments()
+    out = dict(rho=rho, vel=vel, rho0=rho0, steps=np.array(steps), residual=np.array(res),
+               status=np.array(status), seconds=secs)
+    if settle_tol is not None:
+        bt.run(settle_tol, check_every, settle_steps)
+        out["rho_settled"] = bt.moments()[0]
     bt.close()
-    rho = rho.cpu().numpy().reshape(len(specs), side, side)
-    vel = vel.cpu().numpy()[:2].reshape(2, len(specs), side, side).transpose(1, 0, 2, 3)
-    return rho, vel, np.array(steps), np.array(res), np.array(status), secs
-
-
-def mass_momentum_projection(rho_pred, u_pred, rho0):
-    """Give each predicted field the exact mass of its cold start (uniform
-    density shift) and zero total momentum (subtract the mass-weighted mean
-    velocity), keeping the density inside (0, 1/b)."""
-    rho = rho_pred + (rho0.sum(axis=(1, 2)) - rho_pred.sum(axis=(1, 2)))[:, None, None] / \
-        (rho0.shape[1] * rho0.shape[2])
-    rho = np.clip(rho, 1e-3, 0.99 / B_VDW)
-    m = rho.sum(axis=(1, 2))
-    u = u_pred.copy()
-    for a in range(2):
-        mean = (rho * u[:, a]).sum(axis=(1, 2)) / m
-        u[:, a] -= mean[:, None, None]
-    return rho, u
-
-
-def d4_symmetrize(rho, u):
-    """Average (rho [n, Y, X], u [n, 2, Y, X]) over the 8 symmetries of a
-    square about the node (Y/2, X/2): the centred drop and its steady state
-    are invariant under them, so this removes prediction errors that would
-    seed the slow, symmetry-breaking shear modes of the periodic box."""
-    fx = lambda a: np.roll(a[..., :, ::-1], 1, axis=-1)
-    fy = lambda a: np.roll(a[..., ::-1, :], 1, axis=-2)
-    tr = lambda a: np.swapaxes(a, -1, -2)
-    ux, uy = u[:, 0], u[:, 1]
-    imgs = [(rho, ux, uy), (fx(rho), -fx(ux), fx(uy)), (fy(rho), fy(ux), -fy(uy)),
-            (fx(fy(rho)), -fx(fy(ux)), -fx(fy(uy)))]
-    imgs += [(tr(r), tr(b), tr(a)) for r, a, b in imgs]
-    r = sum(i[0] for i in imgs) / 8.0
-    vx = sum(i[1] for i in imgs) / 8.0
-    vy = sum(i[2] for i in imgs) / 8.0
-    return r, np.stack([vx, vy], axis=1)
+    return out
 
 
 def warm_start(net, specs, side, tol=1e-10, check_every=100, max_steps=60000, patience=3,
-               grace=500, symmetrize=True, with_velocity=True):
-    """Predict, project, run with the rising-residual check; problems that
-    diverge are rerun from the cold start.  Returns per-problem total steps,
-    statuses, the fallback mask and wall seconds (inference included)."""
+               grace=500, symmetrize=True, with_velocity=True, settle_tol=None):
+    """Predict, project (lbm_warm_project), run with the rising-residual
+    check; problems that diverge are rerun from the cold start.  Returns the
+    steady_states dict with per-problem total steps, final statuses, the
+    fallback mask and wall seconds including inference."""
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    n = len(specs)
     _, rho0 = problems(specs, side)
-    x = torch.tensor(features(specs, side, rho0), device=net.dev)
-    pred = net.predict(x).cpu().numpy()
-    rho_p, u_p = decode(pred, rho0)
-    # a non-finite prediction falls back to the cold initial field at once
-    bad = ~(np.isfinite(rho_p).all(axis=(1, 2)) & np.isfinite(u_p).all(axis=(1, 2, 3)))
-    rho_p[bad] = rho0[bad]
-    u_p[bad] = 0.0
-    if not with_velocity:
-        u_p[:] = 0.0
-    if symmetrize:
-        rho_p, u_p = d4_symmetrize(rho_p, u_p)
-    rho_p, u_p = mass_momentum_projection(rho_p, u_p, rho0)
+    pred = net.predict(features(specs, side, rho0))
+    rho_p = torch.empty(n * side * side, dtype=torch.float64, device=net.dev)
+    u_p = torch.empty(3, n * side * side, dtype=torch.float64, device=net.dev)
+    lbm.lbm_warm_project(n, side, CP_OUT, pred, rho0, SCALE["drho"], SCALE["u"], with_velocity,
+                         symmetrize, RHO_LO, 0.99 / B_VDW, rho_p, u_p)
+    torch.cuda.synchronize()
     t_inf = time.perf_counter() - t0
-    rho, vel, steps, res, status, secs = steady_states(specs, side, tol, check_every, max_steps,
-                                                       rho_init=rho_p, u_init=u_p,
-                                                       patience=patience, grace=grace)
-    fallback = status == lbm.BATCH_DIVERGED
-    total = steps.copy()
+    run = steady_states(specs, side, tol, check_every, max_steps, rho_init=rho_p, u_init=u_p,
+                        patience=patience, grace=grace, settle_tol=settle_tol)
+    fallback = run["status"] == lbm.BATCH_DIVERGED
+    total = run["steps"].copy()
+    status = run["status"].copy()
     secs_fb = 0.0
     if fallback.any():
         idx = np.nonzero(fallback)[0]
-        sub = [specs[i] for i in idx]
-        _, _, s2, r2, st2, secs_fb = steady_states(sub, side, tol, check_every, max_steps)
-        total[idx] += s2
-        status = status.copy()
-        status[idx] = st2
-    return dict(steps=total, status=status, fallback=fallback, seconds=t_inf + secs + secs_fb,
-                inference_seconds=t_inf, rho=rho, vel=vel)
+        sub = steady_states([specs[i] for i in idx], side, tol, check_every, max_steps)
+        total[idx] += sub["steps"]
+        status[idx] = sub["status"]
+        secs_fb = sub["seconds"]
+    run.update(steps=total, status=status, fallback=fallback, inference_seconds=t_inf,
+               seconds=t_inf + run["seconds"] + secs_fb)
+    return run
 
 
 # ---- end-to-end experiment: generate, train, compare warm vs cold ----------
@@ -266,21 +236,23 @@ def _log(*a):
 
 def generate(nprob, side, seed, batch=512, tol=1e-10, max_steps=60000):
     """Steady states of `nprob` drops from the stable batched workload
-    (side fixed), by the batched runner.  Returns (specs, x, y, steps)."""
+    (side fixed), by the batched runner.  Returns (specs, x, y, steps) with
+    x, y device tensors of the converged problems only."""
     specs = inputs.stable_batch_specs(nprob, seed, side_lo=side, side_hi=side)
     xs, ys, steps, kept = [], [], [], []
     for i in range(0, nprob, batch):
         sub = specs[i:i + batch]
-        rho, vel, st, res, status, secs = steady_states(sub, side, tol, 100, max_steps)
-        _, rho0 = problems(sub, side)
-        ok = status == lbm.BATCH_CONVERGED
-        xs.append(features(sub, side, rho0)[ok])
-        ys.append(targets(rho0, rho, vel)[ok])
-        steps.append(st[ok])
-        kept += [s for s, o in zip(sub, ok) if o]
+        run = steady_states(sub, side, tol, 100, max_steps)
+        ok = np.nonzero(run["status"] == lbm.BATCH_CONVERGED)[0]
+        idx = torch.tensor(ok, device=run["rho"].device)
+        xs.append(features(sub, side, run["rho0"]).index_select(0, idx))
+        ys.append(targets(run["rho"], run["rho0"], run["vel"], side).index_select(0, idx))
+        steps.append(run["steps"][ok])
+        kept += [sub[k] for k in ok]
         _log("generated %d/%d steady states (%.1f s, median steps %d, status counts %s)"
-             % (i + len(sub), nprob, secs, int(np.median(st)), np.bincount(status, minlength=5).tolist()))
-    return kept, np.concatenate(xs), np.concatenate(ys), np.concatenate(steps)
+             % (i + len(sub), nprob, run["seconds"], int(np.median(run["steps"])),
+                np.bincount(run["status"], minlength=5).tolist()))
+    return kept, torch.cat(xs), torch.cat(ys), np.concatenate(steps)
 
 
 def train(net, x, y, epochs, batch=16, lr=1e-3, seed=1):
@@ -301,53 +273,97 @@ def train(net, x, y, epochs, batch=16, lr=1e-3, seed=1):
     return losses
 
 
+def _field_error(rho, ref, n):
+    """Per-problem max relative density difference."""
+    a = rho.reshape(n, -1)
+    b = ref.reshape(n, -1)
+    return ((a - b).abs() / b).amax(dim=1).cpu().numpy()
+
+
+VARIANTS = (("sym", dict()), ("sym_rho_only", dict(with_velocity=False)),
+            ("raw", dict(symmetrize=False)))
+
+
+def evaluate(net, n_eval=512, side=128, seed=6, tol=1e-10, ref_tol=1e-13, ref_steps=120000,
+             variants=VARIANTS):
+    """Cold start versus the warm-start variants on held-out drops, each at
+    the residual `tol`; every final field is compared with a reference run
+    to `ref_tol` (the same cold start, run further)."""
+    specs = inputs.stable_batch_specs(n_eval, seed, side_lo=side, side_hi=side)
+    cold = steady_states(specs, side, tol, settle_tol=ref_tol, settle_steps=ref_steps)
+    ref = dict(rho=cold["rho_settled"])
+    out = dict(n_eval=n_eval, side=side, tol=tol, ref_tol=ref_tol)
+
+    def liquid_fraction(rho):
+        r = rho.reshape(n_eval, -1)
+        mid = 0.5 * (r.amax(dim=1) + r.amin(dim=1))
+        return (r > mid[:, None]).double().mean(dim=1).cpu().numpy()
+
+    lf_ref = liquid_fraction(ref["rho"])
+
+    def summary(run, secs):
+        # err: against the cold start's settled state; err_self: against the
+        # state this run itself settles into (how far from steady it stopped)
+        err = _field_error(run["rho"], ref["rho"], n_eval)
+        err_self = _field_error(run["rho"], run["rho_settled"], n_eval)
+        err_settled = _field_error(run["rho_settled"], ref["rho"], n_eval)
+        conv = run["status"] == lbm.BATCH_CONVERGED
+        lf = liquid_fraction(run["rho_settled"])
+        other = [dict(problem=int(i), err=float(err[i]), err_self=float(err_self[i]),
+                      err_settled=float(err_settled[i]), liquid_fraction=float(lf[i]),
+                      ref_liquid_fraction=float(lf_ref[i]), **specs[i])
+                 for i in np.nonzero(err_settled > 1e-3)[0]]
+        return dict(seconds=secs, steps_total=int(run["steps"].sum()),
+                    steps_median=float(np.median(run["steps"])), steps_max=int(run["steps"].max()),
+                    converged=int(conv.sum()), err_median=float(np.median(err)),
+                    err_p90=float(np.percentile(err, 90)), err_max=float(err.max()),
+                    err_self_median=float(np.median(err_self)), err_self_max=float(err_self.max()),
+                    other_steady_state=other)
+
+    out["cold"] = summary(cold, cold["seconds"])
+    _log("cold: %.2f s, %s" % (cold["seconds"], out["cold"]))
+    for name, kw in variants:
+        w = warm_start(net, specs, side, tol, settle_tol=ref_tol, **kw)
+        out[name] = summary(w, w["seconds"])
+        out[name].update(fallbacks=int(w["fallback"].sum()), inference_seconds=w["inference_seconds"])
+        ratio = w["steps"] / np.maximum(cold["steps"], 1)
+        out[name].update(step_ratio_median=float(np.median(ratio)),
+                         step_ratio_p10=float(np.percentile(ratio, 10)),
+                         step_ratio_p90=float(np.percentile(ratio, 90)))
+        _log("warm[%s]: %.2f s, %s" % (name, w["seconds"], out[name]))
+    return out
+
+
 def run_experiment(n_train=2048, n_eval=512, side=128, epochs=20, seed_train=5, seed_eval=6,
                    tol=1e-10, out_json=None, weights=None):
     t0 = time.perf_counter()
-    _, xtr, ytr, _ = generate(n_train, side, seed_train, tol=tol)
+    _, xt, yt, _ = generate(n_train, side, seed_train, tol=tol)
     t_gen = time.perf_counter() - t0
+    zero_loss = float((yt[..., :OUT_REAL].double() ** 2).mean())
     net = WarmNet(seed=7)
-    dev = net.dev
-    xt, yt = torch.tensor(xtr, device=dev), torch.tensor(ytr, device=dev)
     t1 = time.perf_counter()
     losses = train(net, xt, yt, epochs)
     t_train = time.perf_counter() - t1
     del xt, yt
-    specs = inputs.stable_batch_specs(n_eval, seed_eval, side_lo=side, side_hi=side)
-    cold_rho, _, cold_steps, cold_res, cold_status, cold_secs = steady_states(specs, side, tol)
-    _log("cold: %.2f s, median steps %d" % (cold_secs, int(np.median(cold_steps))))
-    variants = {}
-    for name, kw in (("raw", dict(symmetrize=False)), ("sym_rho_only", dict(with_velocity=False)),
-                     ("sym", dict())):
-        w = warm_start(net, specs, side, tol, **kw)
-        _log("warm[%s]: %.2f s, median steps %d, fallbacks %d"
-             % (name, w["seconds"], int(np.median(w["steps"])), int(w["fallback"].sum())))
-        ok = (w["status"] == lbm.BATCH_CONVERGED) & (cold_status == lbm.BATCH_CONVERGED) & ~w["fallback"]
-        diff = float(np.max(np.abs(w["rho"][ok] - cold_rho[ok]) / cold_rho[ok])) if ok.any() else None
-        variants[name] = dict(seconds=w["seconds"], steps_median=float(np.median(w["steps"])),
-                              steps_total=int(w["steps"].sum()), fallbacks=int(w["fallback"].sum()),
-                              rho_rel_diff_vs_cold=diff)
-    warm = w
-    ratio = warm["steps"] / np.maximum(cold_steps, 1)
-    res = dict(n_train=n_train, n_eval=n_eval, side=side, epochs=epochs, tol=tol,
-               seconds_generate=t_gen, seconds_train=t_train, final_loss=losses[-1], losses=losses,
-               cold_seconds=cold_secs, warm_seconds=warm["seconds"],
-               warm_inference_seconds=warm["inference_seconds"],
-               cold_steps_median=float(np.median(cold_steps)), warm_steps_median=float(np.median(warm["steps"])),
-               cold_steps_total=int(cold_steps.sum()), warm_steps_total=int(warm["steps"].sum()),
-               step_ratio_median=float(np.median(ratio)), step_ratio_p10=float(np.percentile(ratio, 10)),
-               step_ratio_p90=float(np.percentile(ratio, 90)),
-               cold_converged=int((cold_status == lbm.BATCH_CONVERGED).sum()),
-               warm_converged=int((warm["status"] == lbm.BATCH_CONVERGED).sum()),
-               fallbacks=int(warm["fallback"].sum()), variants=variants,
-               zero_prediction_loss=float((ytr[..., :OUT_REAL].astype(np.float64) ** 2).mean()))
+    res = dict(n_train=n_train, epochs=epochs, seconds_generate=t_gen, seconds_train=t_train,
+               final_loss=losses[-1], zero_prediction_loss=zero_loss, losses=losses)
+    if weights:
+        np.savez(weights, *[a for W, b in net.numpy_params() for a in (W, b)])
+    res.update(evaluate(net, n_eval, side, seed_eval, tol))
     if out_json:
         import json
         with open(out_json, "w") as fh:
             json.dump(res, fh, indent=1)
-    if weights:
-        np.savez(weights, *[a for W, b in net.numpy_params() for a in (W, b)])
     return res, net
+
+
+def load_weights(path, device="cuda"):
+    """A WarmNet with the parameters saved by run_experiment."""
+    net = WarmNet(device=device)
+    with np.load(path) as d:
+        arrs = [d["arr_%d" % i] for i in range(len(d.files))]
+    net.load_numpy([(arrs[2 * l], arrs[2 * l + 1]) for l in range(len(arrs) // 2)])
+    return net
 
 
 if __name__ == "__main__":
@@ -360,7 +376,16 @@ if __name__ == "__main__":
     ap.add_argument("--epochs", type=int, default=20)
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--out", default=None)
-    ap.add_argument("--weights", default=None)
+    ap.add_argument("--weights", default=None, help="where to save the trained parameters")
+    ap.add_argument("--evaluate", default=None, metavar="WEIGHTS",
+                    help="only evaluate saved parameters on the held-out drops")
     a = ap.parse_args()
-    r, _ = run_experiment(a.train, a.eval, a.side, a.epochs, tol=a.tol, out_json=a.out, weights=a.weights)
+    if a.evaluate:
+        r = evaluate(load_weights(a.evaluate), a.eval, a.side, tol=a.tol)
+        if a.out:
+            with open(a.out, "w") as fh:
+                json.dump(r, fh, indent=1)
+    else:
+        r, _ = run_experiment(a.train, a.eval, a.side, a.epochs, tol=a.tol, out_json=a.out,
+                              weights=a.weights)
     print(json.dumps({k: v for k, v in r.items() if k != "losses"}))

@@ -94,3 +94,56 @@ def test_training_reduces_loss():
     for _ in range(150):
         l1 = net.train_step(tx, ty, 1e-3)
     assert l1 < 0.2 * l0
+
+
+def test_warm_features_and_targets_match_reference():
+    from oracle import warmprep
+    from paper_0710_5470_amd import lbm
+    _say("warm features/targets")
+    rng = np.random.default_rng(21)
+    n, side = 3, 24
+    consts = rng.normal(size=(n, 5))
+    rho0 = 2.5 + rng.random((n, side, side))
+    rho = rho0 + 0.1 * rng.normal(size=rho0.shape)
+    vel = 1e-3 * rng.normal(size=(n, 2, side, side))
+    dev = torch.device("cuda")
+    t_rho0 = torch.tensor(rho0.reshape(-1), device=dev)
+    x = torch.empty(n, side, side, 16, device=dev)
+    lbm.lbm_warm_features(n, side, torch.tensor(consts, device=dev), t_rho0, 3.5, 1.0, x)
+    v3 = np.zeros((3, n * side * side))
+    v3[0] = vel[:, 0].reshape(-1)
+    v3[1] = vel[:, 1].reshape(-1)
+    y = torch.empty(n, side, side, 16, device=dev)
+    lbm.lbm_warm_targets(torch.tensor(rho.reshape(-1), device=dev), t_rho0, torch.tensor(v3, device=dev),
+                         0.2, 1e-3, y)
+    torch.cuda.synchronize()
+    assert np.array_equal(x.cpu().numpy(), warmprep.features(consts, rho0, 3.5, 1.0))
+    assert np.array_equal(y.cpu().numpy(), warmprep.targets(rho, rho0, vel, 0.2, 1e-3))
+
+
+@pytest.mark.parametrize("side,sym,with_u", [(32, True, True), (32, True, False), (31, True, True),
+                                             (20, False, True)])
+def test_warm_projection_matches_reference(side, sym, with_u):
+    from oracle import warmprep
+    from paper_0710_5470_amd import lbm
+    _say("warm projection", side, sym, with_u)
+    rng = np.random.default_rng(side)
+    n = 4
+    rho0 = 2.5 + rng.random((n, side, side))
+    pred = rng.normal(size=(n, side, side, 16)).astype(np.float32)
+    pred[2, 3, 4, 1] = np.nan  # problem 2 falls back when the velocity is used
+    pred[1, 0, 0, 0] = 200.0   # clamped
+    dev = torch.device("cuda")
+    rho = torch.empty(n * side * side, dtype=torch.float64, device=dev)
+    u = torch.empty(3, n * side * side, dtype=torch.float64, device=dev)
+    lbm.lbm_warm_project(n, side, 16, torch.tensor(pred, device=dev),
+                         torch.tensor(rho0.reshape(-1), device=dev), 0.2, 1e-3, with_u, sym, 1e-3, 10.0,
+                         rho, u)
+    torch.cuda.synchronize()
+    rr, ur = warmprep.project(pred, rho0, 0.2, 1e-3, with_u, sym, 1e-3, 10.0)
+    r_g = rho.cpu().numpy().reshape(n, side, side)
+    u_g = u.cpu().numpy()
+    assert np.max(np.abs(r_g - rr) / rr) < 1e-13
+    for a in range(2):
+        assert np.max(np.abs(u_g[a].reshape(n, side, side) - ur[:, a])) < 1e-17 + 1e-12 * np.abs(ur).max()
+    assert np.all(u_g[2] == 0.0)
