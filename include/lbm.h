@@ -233,6 +233,11 @@ int lbm_batch_step(lbm_batch *bt, long long nsteps);
 int lbm_batch_run(lbm_batch *bt, double tol, int check_every, long long max_steps, int patience,
                   long long grace, long long *host_steps, double *host_residual, int *host_status);
 
+/* Make every problem active again with a fresh status (step count,
+ * residual history), keeping its populations, so that a later lbm_batch_run
+ * continues all of them (e.g. to a tighter residual).  Synchronises. */
+int lbm_batch_reactivate(lbm_batch *bt);
+
 /* Density [n_total] and velocity [3][n_total] of every problem (retired ones
  * included).  Only enqueues. */
 int lbm_batch_moments(lbm_batch *bt, double *dev_rho, double *dev_vel);

@@ -401,6 +401,24 @@ int lbm_batch_run(lbm_batch *bt, double tol, int check_every, long long max_step
     return LBM_OK;
 }
 
+int lbm_batch_reactivate(lbm_batch *bt)
+{
+    if (!bt) return LBM_E_INVAL;
+    std::vector<BatchState> st(bt->nprob);
+    std::vector<int> ones(bt->nprob, 1);
+    for (auto &s : st) {
+        s = BatchState{};
+        s.active = 1;
+    }
+    if (hipMemcpyAsync(bptr<BatchState>(bt, bt->o_state), st.data(), st.size() * sizeof(BatchState),
+                       hipMemcpyHostToDevice, bt->stream) != hipSuccess ||
+        hipMemcpyAsync(bptr<int>(bt, bt->o_act), ones.data(), ones.size() * 4, hipMemcpyHostToDevice,
+                       bt->stream) != hipSuccess ||
+        hipStreamSynchronize(bt->stream) != hipSuccess)
+        return LBM_E_DEVICE;
+    return LBM_OK;
+}
+
 int lbm_batch_moments(lbm_batch *bt, double *dev_rho, double *dev_vel)
 {
     if (!bt || !dev_rho || !dev_vel) return LBM_E_INVAL;

@@ -12,7 +12,7 @@
 #include <cstring>
 #include <new>
 
-#include "../../include/lbm.h"
+#include "lbm.h"  // include/, on the include path
 #include "lbm_aux.h"
 #include "lbm_step.h"
 

@@ -60,10 +60,12 @@ __device__ __forceinline__ double buf_load(__amdgpu_buffer_rsrc_t r, unsigned vo
 {
     return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
 }
-// Cache policy of the population stores (0: default).  The stored state is
-// read again only in the next step, long after it has left the caches.
+// Cache policy of the population stores: 2 sets the non-temporal bit (nt),
+// so the stores stream past the caches instead of evicting the neighbour
+// populations that halo loads re-read (the stored state is read again only
+// in the next step, long after it has left the caches).
 #ifndef LBM_STORE_CPOL
-#define LBM_STORE_CPOL 0
+#define LBM_STORE_CPOL 2
 #endif
 
 __device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, float v)

@@ -80,6 +80,7 @@ _sig = {
     "lbm_batch_run": (ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_int, ctypes.c_longlong,
                                      ctypes.c_int, ctypes.c_longlong,
                                      ctypes.POINTER(ctypes.c_longlong), _dp, _ip]),
+    "lbm_batch_reactivate": (ctypes.c_int, [_vp]),
     "lbm_batch_moments": (ctypes.c_int, [_vp, _vp, _vp]),
     "lbm_batch_offset": (ctypes.c_longlong, [_vp, ctypes.c_int]),
     "lbm_batch_set_launch": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int]),
@@ -305,6 +306,10 @@ def lbm_batch_get_launch(bt):
     return t.value, p.value, w.value
 
 
+def lbm_batch_reactivate(bt):
+    _check(_L.lbm_batch_reactivate(bt), "lbm_batch_reactivate")
+
+
 def lbm_batch_destroy(bt):
     _check(_L.lbm_batch_destroy(bt), "lbm_batch_destroy")
 
@@ -404,6 +409,9 @@ class Batch:
 
     def step(self, n):
         lbm_batch_step(self.bt, n)
+
+    def reactivate(self):
+        lbm_batch_reactivate(self.bt)
 
     def moments(self):
         with torch.cuda.stream(self.stream):

@@ -188,6 +188,7 @@ def steady_states(specs, side, tol=1e-10, check_every=100, max_steps=60000, rho_
     out = dict(rho=rho, vel=vel, rho0=rho0, steps=np.array(steps), residual=np.array(res),
                status=np.array(status), seconds=secs)
     if settle_tol is not None:
+        bt.reactivate()
         bt.run(settle_tol, check_every, settle_steps)
         out["rho_settled"] = bt.moments()[0]
     bt.close()
@@ -195,7 +196,7 @@ def steady_states(specs, side, tol=1e-10, check_every=100, max_steps=60000, rho_
 
 
 def warm_start(net, specs, side, tol=1e-10, check_every=100, max_steps=60000, patience=3,
-               grace=500, symmetrize=True, with_velocity=True, settle_tol=None):
+               grace=500, symmetrize=True, with_velocity=False, settle_tol=None):
     """Predict, project (lbm_warm_project), run with the rising-residual
     check; problems that diverge are rerun from the cold start.  Returns the
     steady_states dict with per-problem total steps, final statuses, the
@@ -280,8 +281,10 @@ def _field_error(rho, ref, n):
     return ((a - b).abs() / b).amax(dim=1).cpu().numpy()
 
 
-VARIANTS = (("sym", dict()), ("sym_rho_only", dict(with_velocity=False)),
-            ("raw", dict(symmetrize=False)))
+# rho: the default (symmetrised density, u = 0); rho_u: with the predicted
+# velocity; raw: no symmetrisation
+VARIANTS = (("rho", dict()), ("rho_u", dict(with_velocity=True)),
+            ("raw", dict(symmetrize=False, with_velocity=True)))
 
 
 def evaluate(net, n_eval=512, side=128, seed=6, tol=1e-10, ref_tol=1e-13, ref_steps=120000,

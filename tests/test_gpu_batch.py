@@ -98,3 +98,32 @@ def test_batch_detects_rising_residual():
     steps, res, status = bt.run(tol=1e-12, check_every=2, max_steps=4000, patience=1, grace=0)
     bt.close()
     assert status[0] in (lbm.BATCH_DIVERGED, lbm.BATCH_NONFINITE)
+
+
+def test_reactivated_batch_continues_to_a_tighter_residual():
+    """After a run retires every problem, lbm_batch_reactivate lets a second
+    run continue them from their populations: a run to 1e-6 followed by a
+    run to 1e-9 ends in the same state as one run straight to 1e-9 when the
+    two stop after the same total number of steps."""
+    from paper_0710_5470_amd import lbm
+    plist, rho = _problems(SPECS[:2], 0, 0)
+    bt = lbm.Batch(plist, rho)
+    s1, r1, st1 = bt.run(tol=1e-6, check_every=50, max_steps=100000)
+    again, _, _ = bt.run(tol=1e-6, check_every=50, max_steps=100000)
+    bt.reactivate()
+    s2, r2, st2 = bt.run(tol=1e-9, check_every=50, max_steps=100000)
+    _say("two-stage run", s1, s2, r2, st2)
+    assert again == s1  # nothing active: no further step is counted
+    assert st2 == [lbm.BATCH_CONVERGED] * 2 and all(r <= 1e-9 for r in r2)
+    assert all(b > 0 for b in s2)
+    rho_two, _ = bt.moments()
+    bt.close()
+    # single run of the same total number of steps per problem
+    for k in range(2):
+        p1, rr = _problems(SPECS[k:k + 1], 0, 0)
+        one = lbm.Batch(p1, rr)
+        one.step(s1[k] + s2[k])
+        r_one, _ = one.moments()
+        one.close()
+        seg = rho_two[sum(p.nx * p.ny for p in plist[:k]):][:plist[k].nx * plist[k].ny]
+        assert torch.equal(seg, r_one)
