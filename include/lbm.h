@@ -233,6 +233,14 @@ int lbm_batch_step(lbm_batch *bt, long long nsteps);
 int lbm_batch_run(lbm_batch *bt, double tol, int check_every, long long max_steps, int patience,
                   long long grace, long long *host_steps, double *host_residual, int *host_status);
 
+/* Per-problem spurious velocity of the current state: host_out[k] = max |u|
+ * (equilibrium scheme) or max |v| (forcing scheme, v = u + g / 2 rho) over
+ * problem k's sites, the same quantity as lbm_max_spurious_u (section
+ * "Numerical results": the maximum velocity magnitude in the system).
+ * A problem with a non-finite velocity reports +inf, and the call then
+ * returns LBM_E_NONFINITE (host_out is filled either way).  Synchronises. */
+int lbm_batch_max_spurious_u(lbm_batch *bt, double *host_out);
+
 /* Make every problem active again with a fresh status (step count,
  * residual history), keeping its populations, so that a later lbm_batch_run
  * continues all of them (e.g. to a tighter residual).  Synchronises. */

@@ -51,6 +51,31 @@ __global__ __launch_bounds__(RED_THREADS) void batch_field_stats_kernel(const lo
         for (int j = 0; j < 4; j++) out[4 * k + j] = v[j];
 }
 
+// One workgroup per problem: max |vel| over the problem's sites and the
+// number of non-finite velocity entries (written to out[2k], out[2k + 1]).
+__global__ __launch_bounds__(RED_THREADS) void batch_maxvel_kernel(const long long *off,
+                                                                   const long long *nsite, long long stride,
+                                                                   const double *__restrict__ vel,
+                                                                   double *__restrict__ out)
+{
+    const int k = blockIdx.x;
+    const long long o = off[k], n = nsite[k];
+    double v[2] = {0.0, 0.0};
+    const int ops[2] = {RED_MAX, RED_SUM};
+    for (long long s = threadIdx.x; s < n; s += RED_THREADS) {
+        const long long q = o + s;
+        const double a0 = vel[q], a1 = vel[stride + q], a2 = vel[2 * stride + q];
+        const double sp = sqrt(a0 * a0 + a1 * a1 + a2 * a2);
+        v[0] = isfinite(sp) ? fmax(v[0], sp) : INFINITY;
+        v[1] += isfinite(sp) ? 0.0 : 1.0;
+    }
+    block_reduce<2>(v, ops);
+    if (threadIdx.x == 0) {
+        out[2 * k] = v[0];
+        out[2 * k + 1] = v[1];
+    }
+}
+
 __global__ void batch_zero_kernel(int *counter)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0;

@@ -426,6 +426,27 @@ int lbm_batch_moments(lbm_batch *bt, double *dev_rho, double *dev_vel)
     return hipGetLastError() == hipSuccess ? LBM_OK : LBM_E_DEVICE;
 }
 
+int lbm_batch_max_spurious_u(lbm_batch *bt, double *host_out)
+{
+    if (!bt || !host_out) return LBM_E_INVAL;
+    double *vel = bptr<double>(bt, bt->o_vel), *stats = bptr<double>(bt, bt->o_stats);
+    batch_step(bt, 0, 1, bptr<double>(bt, bt->o_rho), vel, bptr<int>(bt, bt->o_all));
+    batch_maxvel_kernel<<<bt->nprob, RED_THREADS, 0, bt->stream>>>(
+        bptr<long long>(bt, bt->o_off), bptr<long long>(bt, bt->o_ns), bt->ntot, vel, stats);
+    std::vector<double> h(2 * (size_t)bt->nprob);
+    if (hipGetLastError() != hipSuccess ||
+        hipMemcpyAsync(h.data(), stats, h.size() * sizeof(double), hipMemcpyDeviceToHost, bt->stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(bt->stream) != hipSuccess)
+        return LBM_E_DEVICE;
+    bool bad = false;
+    for (int k = 0; k < bt->nprob; k++) {
+        host_out[k] = h[2 * k];
+        bad = bad || h[2 * k + 1] != 0.0;
+    }
+    return bad ? LBM_E_NONFINITE : LBM_OK;
+}
+
 long long lbm_batch_offset(const lbm_batch *bt, int k)
 {
     if (!bt || k < 0 || k > bt->nprob) return -1;

@@ -81,6 +81,7 @@ _sig = {
                                      ctypes.c_int, ctypes.c_longlong,
                                      ctypes.POINTER(ctypes.c_longlong), _dp, _ip]),
     "lbm_batch_reactivate": (ctypes.c_int, [_vp]),
+    "lbm_batch_max_spurious_u": (ctypes.c_int, [_vp, _dp]),
     "lbm_batch_moments": (ctypes.c_int, [_vp, _vp, _vp]),
     "lbm_batch_offset": (ctypes.c_longlong, [_vp, ctypes.c_int]),
     "lbm_batch_set_launch": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int]),
@@ -306,6 +307,16 @@ def lbm_batch_get_launch(bt):
     return t.value, p.value, w.value
 
 
+def lbm_batch_max_spurious_u(bt, nprob):
+    """Per-problem max |u| (or |v|); inf for a problem whose state is not
+    finite."""
+    out = (ctypes.c_double * nprob)()
+    rc = _L.lbm_batch_max_spurious_u(bt, out)
+    if rc not in (OK, E_NONFINITE):
+        _check(rc, "lbm_batch_max_spurious_u")
+    return list(out)
+
+
 def lbm_batch_reactivate(bt):
     _check(_L.lbm_batch_reactivate(bt), "lbm_batch_reactivate")
 
@@ -412,6 +423,9 @@ class Batch:
 
     def reactivate(self):
         lbm_batch_reactivate(self.bt)
+
+    def max_spurious_u(self):
+        return lbm_batch_max_spurious_u(self.bt, self.nprob)
 
     def moments(self):
         with torch.cuda.stream(self.stream):

@@ -316,12 +316,15 @@ def evaluate(net, n_eval=512, side=128, seed=6, tol=1e-10, ref_tol=1e-13, ref_st
                       err_settled=float(err_settled[i]), liquid_fraction=float(lf[i]),
                       ref_liquid_fraction=float(lf_ref[i]), **specs[i])
                  for i in np.nonzero(err_settled > 1e-3)[0]]
+        # statistics over the problems whose cold reference is finite
+        fin = np.isfinite(err_settled)
         return dict(seconds=secs, steps_total=int(run["steps"].sum()),
                     steps_median=float(np.median(run["steps"])), steps_max=int(run["steps"].max()),
-                    converged=int(conv.sum()), err_median=float(np.median(err)),
-                    err_p90=float(np.percentile(err, 90)), err_max=float(err.max()),
-                    err_self_median=float(np.median(err_self)), err_self_max=float(err_self.max()),
-                    other_steady_state=other)
+                    converged=int(conv.sum()), compared=int(fin.sum()),
+                    err_median=float(np.median(err[fin])), err_p90=float(np.percentile(err[fin], 90)),
+                    err_max=float(err[fin].max()), err_self_median=float(np.median(err_self[fin])),
+                    err_self_max=float(err_self[fin].max()),
+                    unsettled=int((err_self[fin] > 1e-3).sum()), other_steady_state=other)
 
     out["cold"] = summary(cold, cold["seconds"])
     _log("cold: %.2f s, %s" % (cold["seconds"], out["cold"]))
