@@ -37,6 +37,20 @@ WORKLOADS = {
 KERNEL_SOURCES = ["paper_0710_5470_amd/csrc/lbm_step.h", "paper_0710_5470_amd/csrc/lbm_lattice.h"]
 
 
+def make_workload(wl):
+    """lbm_params and the initial density of a named workload."""
+    from paper_0710_5470_amd import inputs, lbm
+    q, scheme, storage, compute, shape, T, kappa, tau, R, noise = WORKLOADS[wl]
+    g, l = lbm.lbm_coexistence(A_VDW, B_VDW, T)
+    if q == 19:
+        rho0 = inputs.sphere_with_noise(shape[0], R, g, l, noise, 3)
+    else:
+        rho0, _, _ = inputs.multi_drop(shape, 64, 8.0, 48.0, g, l, seed=2)
+    p = lbm.params(lattice=q, scheme=scheme, storage=storage, shape=shape, T=T, kappa=kappa,
+                   tau=tau, compute=compute)
+    return p, rho0
+
+
 def kernel_hash():
     h = hashlib.sha256()
     for rel in KERNEL_SOURCES:
@@ -119,7 +133,7 @@ def main():
                          "calibration for rocprofv3 --pmc)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
@@ -130,13 +144,7 @@ def main():
 
     wl = args.workload
     q, scheme, storage, compute, shape, T, kappa, tau, R, noise = WORKLOADS[wl]
-    g, l = lbm.lbm_coexistence(A_VDW, B_VDW, T)
-    if q == 19:
-        rho0 = inputs.sphere_with_noise(shape[0], R, g, l, noise, 3)
-    else:
-        rho0, _, _ = inputs.multi_drop(shape, 64, 8.0, 48.0, g, l, seed=2)
-    p = lbm.params(lattice=q, scheme=scheme, storage=storage, shape=shape, T=T, kappa=kappa,
-                   tau=tau, compute=compute)
+    p, rho0 = make_workload(wl)
     sim = lbm.Simulation(p, rho0)
     n = sim.n
     tune = None

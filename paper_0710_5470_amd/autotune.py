@@ -27,7 +27,7 @@ def _key(p):
 
 def candidates(p):
     np_ = p.nz if p.lattice == lbm.D3Q19 else p.ny
-    planes = sorted(set(min(c, np_) for c in (8, 16, 32, 64)))
+    planes = sorted(set(min(c, np_) for c in (8, 16, 32, 64, 128, 256)))
     return [(t, c) for t in range(lbm.lbm_tile_count(p.lattice)) for c in planes]
 
 

@@ -1,0 +1,92 @@
+"""Parity at the benchmark's full sizes, in the launch configuration bench.py
+times (autotuned), on sampled sites the oracle computes one by one.
+
+For each workload of bench.py the GPU runs a few steps from its initial
+state; the state before the last step (FP64 export, the paper's post-stream
+f_i(r, t)) goes to the oracle's site-local collision (oracle.collide_sites),
+and the oracle's post-collision f*_i(r) must equal the GPU's post-stream
+f_i(r + e_i, t + 1) at every sampled site and direction.  The sample holds
+every combination of tile, chunk and periodic-wrap boundary coordinates of
+the launch plus seeded random sites.
+
+Tolerances (absolute, on populations of magnitude <= 1):
+  FP64 storage: 1e-13 (the oracle and the GPU evaluate the same formulas in
+    FP64 from the same inputs; FMA contraction and summation order differ).
+  FP32 storage, FP32 arithmetic: 1e-5, derived: a population is the sum of
+    about 30 rounded FP32 operations whose intermediate magnitudes are at
+    most the van der Waals pressure p0 ~ 4 (ulp 4.8e-7), so the accumulated
+    rounding is below 30 x 0.5 x 4.8e-7 = 7.2e-6.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+ROOT = os.path.join(os.path.dirname(__file__), "..")
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+CASES = [("d3q19_256_fp32_force", 1e-5), ("d3q19_256_fp64_force", 1e-13),
+         ("d2q9_1024_fp64_eq", 1e-13), ("d2q9_1024_fp32_force", 1e-5)]
+
+
+def _sites(shape, tile, planes, seed, nrand=1500):
+    nx, ny = shape[0], shape[1]
+    nz = shape[2] if len(shape) > 2 else 1
+    tx, ty = tile
+
+    def edges(n, t):
+        v = {0, n - 1}
+        for b in range(t, n, t):
+            v |= {b - 1, b}
+        return sorted(v)
+
+    if nz > 1:
+        xs, ys, zs = edges(nx, tx), edges(ny, ty), edges(nz, planes)
+    else:  # D2Q9: rows of tx sites, planes along y
+        xs, ys, zs = edges(nx, tx), edges(ny, planes), [0]
+    rng = np.random.default_rng(seed)
+    pick = lambda v, k: list(rng.choice(v, size=min(k, len(v)), replace=False))
+    fixed = [(x, y, z) for x in pick(xs, 6) for y in pick(ys, 6) for z in pick(zs, 4)]
+    rand = np.stack([rng.integers(0, nx, nrand), rng.integers(0, ny, nrand),
+                     rng.integers(0, nz, nrand)], axis=1)
+    return np.concatenate([np.array(fixed), rand]).astype(np.int32)
+
+
+@pytest.mark.parametrize("wl,tol", CASES)
+def test_full_size_step_matches_oracle_on_sampled_sites(wl, tol):
+    import bench
+    import oracle
+    from paper_0710_5470_amd import autotune, lbm
+    print("[gpu-case] full-size sampled parity", wl, flush=True)
+    q, scheme, storage, compute, shape, T, kappa, tau, R, noise = bench.WORKLOADS[wl]
+    p, rho0 = bench.make_workload(wl)
+    sim = lbm.Simulation(p, rho0)
+    autotune.autotune(sim, use_cache=False)
+    tile_i, planes, _ = sim.launch()
+    tile = lbm.lbm_tile_shape(q, tile_i)
+    print("[gpu-case] launch tile", tile, "planes", planes, flush=True)
+    sim.step(5)
+    f0 = sim.get_state().cpu().numpy()
+    sim.step(1)
+    f1 = sim.get_state().cpu().numpy()
+    sim.close()
+    op = oracle.params(q=q, scheme=scheme, shape=shape, T=T, kappa=kappa, tau=tau)
+    xyz = _sites(shape, tile, planes, seed=17)
+    fs = oracle.collide_sites(op, f0, xyz)
+    e = oracle.tables(op)["e"]
+    nx, ny = shape[0], shape[1]
+    nz = shape[2] if len(shape) > 2 else 1
+    worst = 0.0
+    for i in range(q):
+        d = (((xyz[:, 2] + e[i][2]) % nz) * ny + (xyz[:, 1] + e[i][1]) % ny) * nx + \
+            (xyz[:, 0] + e[i][0]) % nx
+        worst = max(worst, float(np.max(np.abs(f1[i, d] - fs[:, i]))))
+    print("[gpu-case] %s: %d sites, max |f_gpu - f_oracle| = %.3e (tol %.0e), max |f| %.3f"
+          % (wl, len(xyz), worst, tol, float(np.abs(f1).max())), flush=True)
+    assert np.isfinite(f1).all()
+    assert worst < tol
