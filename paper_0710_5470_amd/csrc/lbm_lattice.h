@@ -47,6 +47,20 @@ template <class L> __host__ __device__ constexpr int ecomp(int i, int a)
 {
     return a == 0 ? L::ex[i] : (a == 1 ? L::ey[i] : L::ez[i]);
 }
+// the velocity opposite to e_i
+template <class L> __host__ __device__ constexpr int opp(int i)
+{
+    for (int j = 0; j < L::Q; j++)
+        if (L::ex[j] == -L::ex[i] && L::ey[j] == -L::ey[i] && L::ez[j] == -L::ez[i]) return j;
+    return -1;
+}
+// the first velocity of the off-axis (diagonal / edge) weight class
+template <class L> __host__ __device__ constexpr int first_off()
+{
+    for (int j = 1; j < L::Q; j++)
+        if (nnz<L>(j) > 1) return j;
+    return -1;
+}
 
 // Runtime coefficients of one problem (host fills them; see lbm_capi.hip).
 template <class R> struct Coefs {
@@ -86,84 +100,170 @@ template <class L, class R> __device__ __forceinline__ R coef_force(const Coefs<
     return nnz<L>(i) == 1 ? c.Ef : c.Ff;
 }
 
-// van der Waals bulk pressure, Eq. (p0), and c_s^2 = dp0/drho (FP64).
-template <class R> __device__ __forceinline__ double vdw_p0(const Coefs<R> &c, double rho)
+// van der Waals bulk pressure, Eq. (p0), and c_s^2 = dp0/drho (FP64), from
+// one reciprocal of 1 - b rho.
+template <class R> __device__ __forceinline__ void vdw(const Coefs<R> &c, double rho, double &p0, double &cs2)
 {
-    return rho * c.T / (1.0 - c.b * rho) - c.a * rho * rho;
+    const double inv = 1.0 / (1.0 - c.b * rho);
+    const double tinv = c.T * inv;
+    p0 = rho * tinv - c.a * rho * rho;
+    cs2 = tinv * inv - 2.0 * c.a * rho;
 }
-template <class R> __device__ __forceinline__ double vdw_cs2(const Coefs<R> &c, double rho)
+
+// Site quantities the equilibrium of Eq. (equilibrium) needs for every
+// direction.  rho_dev = rho - sum_i s_i (rho itself when s = 0); j:
+// momentum; d: discrete gradient of rho; lap: discrete Laplacian.
+template <class R> struct EqSite {
+    R rho, u[3], lam, ud, trX3, klap;
+    R M[3], Mxy, Myz, Mzx;  // kappa d_a rho d_b rho (equilibrium scheme)
+    R st_ax, st_off;        // static part w^p_i p0 - s_i per weight class
+};
+
+template <class L, bool WITH_M, class R>
+__device__ __forceinline__ EqSite<R> eq_site(const Coefs<R> &c, R rho_dev, const R j[3], const R d[3], R lap)
 {
-    double d = 1.0 - c.b * rho;
-    return c.T / (d * d) - 2.0 * c.a * rho;
+    constexpr int DIM = L::DIM;
+    EqSite<R> s;
+    const double rho_d = double(rho_dev) + c.shift_sum;
+    s.rho = R(rho_d);
+    const R inv_rho = R(1) / s.rho;
+    s.u[0] = j[0] * inv_rho;
+    s.u[1] = j[1] * inv_rho;
+    s.u[2] = DIM == 3 ? j[2] * inv_rho : R(0);
+    double p0, cs2;
+    vdw(c, rho_d, p0, cs2);
+    s.lam = c.lambda_on ? R(c.nu * (1.0 - 3.0 * cs2)) : R(0);
+    s.ud = s.u[0] * d[0] + s.u[1] * d[1] + (DIM == 3 ? s.u[2] * d[2] : R(0));
+    const R uu = s.u[0] * s.u[0] + s.u[1] * s.u[1] + (DIM == 3 ? s.u[2] * s.u[2] : R(0));
+    // trace of X_ab = rho u_a u_b + lam (u_a d_b + u_b d_a + delta_ab u.d)
+    s.trX3 = (s.rho * uu + s.lam * R(2 + DIM) * s.ud) * R(1.0 / 3.0);
+    s.klap = c.kappa * s.rho * lap;
+    if (WITH_M) {
+        s.M[0] = c.kappa * d[0] * d[0];
+        s.M[1] = c.kappa * d[1] * d[1];
+        s.M[2] = DIM == 3 ? c.kappa * d[2] * d[2] : R(0);
+        s.Mxy = c.kappa * d[0] * d[1];
+        s.Myz = DIM == 3 ? c.kappa * d[1] * d[2] : R(0);
+        s.Mzx = DIM == 3 ? c.kappa * d[2] * d[0] : R(0);
+    }
+    // the storage shift is the same within a weight class
+    s.st_ax = R(c.wp_ax_d * p0 - c.shift[1]);
+    s.st_off = R(c.wp_off_d * p0 - c.shift[first_off<L>()]);
+    return s;
+}
+
+// Equilibrium of velocity i >= 1 split into the part even in e_i (second
+// moment terms, static part, gradient terms) and the odd part w_i e_i.j:
+// f_i^eq - s_i = even + odd and f_opp(i)^eq - s_opp(i) = even - odd.
+template <class L, bool WITH_M, class R>
+__device__ __forceinline__ void eq_pair(const Coefs<R> &c, const EqSite<R> &s, int i, const R j[3],
+                                        const R d[3], R &even, R &odd)
+{
+    const int e0 = L::ex[i], e1 = L::ey[i], e2 = L::ez[i];
+    const bool axis = nnz<L>(i) == 1;
+    R eu = R(e0) * s.u[0] + R(e1) * s.u[1] + R(e2) * s.u[2];
+    R ed = R(e0) * d[0] + R(e1) * d[1] + R(e2) * d[2];
+    R ej = R(e0) * j[0] + R(e1) * j[1] + R(e2) * j[2];
+    R ee = R(nnz<L>(i));
+    // sum_ab (e_a e_b - delta_ab / 3) X_ab
+    R eXe = s.rho * eu * eu + s.lam * (R(2) * eu * ed + ee * s.ud);
+    R w = axis ? c.w_ax : c.w_off;
+    R v = (axis ? s.st_ax : s.st_off) + w * R(1.5) * (eXe - s.trX3);
+    v -= (axis ? c.wt_ax : c.wt_off) * s.klap;
+    if (WITH_M) {
+        R m = R(0);
+#pragma unroll
+        for (int a = 0; a < L::DIM; a++) {
+            const bool touches = ecomp<L>(i, a) != 0;
+            R wa = axis ? (touches ? c.wm_para : c.wm_perp) : (touches ? c.wm_in : c.wm_out);
+            m += wa * s.M[a];
+        }
+        // off-diagonal weights e_a e_b / 4 (constraint list after Eq. (fi))
+        if (e0 * e1 != 0) m += R(0.25 * e0 * e1) * s.Mxy;
+        if (e1 * e2 != 0) m += R(0.25 * e1 * e2) * s.Myz;
+        if (e2 * e0 != 0) m += R(0.25 * e2 * e0) * s.Mzx;
+        v += m;
+    }
+    even = v;
+    odd = w * ej;
 }
 
 // Equilibrium of Eq. (equilibrium) for i >= 1 and Eq. (feq0) for i = 0,
-// returned as deviations from the storage shift: out_i = f_i^eq - s_i.
-// rho_dev = rho - sum_i s_i (rho itself when s = 0); j: momentum;
-// d: discrete gradient of rho; lap: discrete Laplacian.  The rest
-// deviation is rho_dev - sum_{i>=1} out_i, so the shift never enters the
-// mass balance.  WITH_M adds the kappa d_a rho d_b rho terms (equilibrium
-// scheme only).  Returns rho.
+// returned as deviations from the storage shift: out_i = f_i^eq - s_i.  The
+// rest deviation is rho_dev - sum_{i>=1} out_i, so the shift never enters
+// the mass balance.  WITH_M adds the kappa d_a rho d_b rho terms
+// (equilibrium scheme only).  Returns rho.
 template <class L, bool WITH_M, class R>
 __device__ __forceinline__ R equilibrium(const Coefs<R> &c, R rho_dev, const R j[3], const R d[3],
                                          R lap, R feq[L::Q])
 {
-    constexpr int DIM = L::DIM;
-    const double rho_d = double(rho_dev) + c.shift_sum;
-    const R rho = R(rho_d);
-    R inv_rho = R(1) / rho;
-    R u[3] = {j[0] * inv_rho, j[1] * inv_rho, DIM == 3 ? j[2] * inv_rho : R(0)};
-    const double p0 = vdw_p0(c, rho_d);
-    R lam = c.lambda_on ? R(c.nu * (1.0 - 3.0 * vdw_cs2(c, rho_d))) : R(0);
-    R ud = u[0] * d[0] + u[1] * d[1] + (DIM == 3 ? u[2] * d[2] : R(0));
-    R uu = u[0] * u[0] + u[1] * u[1] + (DIM == 3 ? u[2] * u[2] : R(0));
-    // trace of X_ab = rho u_a u_b + lam (u_a d_b + u_b d_a + delta_ab u.d)
-    R trX = rho * uu + lam * R(2 + DIM) * ud;
-    R klap = c.kappa * rho * lap;
-    R M[3] = {c.kappa * d[0] * d[0], c.kappa * d[1] * d[1], DIM == 3 ? c.kappa * d[2] * d[2] : R(0)};
-    R Mxy = c.kappa * d[0] * d[1];
-    R Myz = DIM == 3 ? c.kappa * d[1] * d[2] : R(0);
-    R Mzx = DIM == 3 ? c.kappa * d[2] * d[0] : R(0);
+    const EqSite<R> s = eq_site<L, WITH_M>(c, rho_dev, j, d, lap);
+    // opposite velocities share the even terms: each pair is evaluated once
     R sum = R(0);
 #pragma unroll
     for (int i = 1; i < L::Q; i++) {
-        const int e0 = L::ex[i], e1 = L::ey[i], e2 = L::ez[i];
-        const bool axis = nnz<L>(i) == 1;
-        R eu = R(e0) * u[0] + R(e1) * u[1] + R(e2) * u[2];
-        R ed = R(e0) * d[0] + R(e1) * d[1] + R(e2) * d[2];
-        R ej = R(e0) * j[0] + R(e1) * j[1] + R(e2) * j[2];
-        R ee = R(nnz<L>(i));
-        // sum_ab (e_a e_b - delta_ab / 3) X_ab
-        R eXe = rho * eu * eu + lam * (R(2) * eu * ed + ee * ud);
-        R w = axis ? c.w_ax : c.w_off;
-        R v = w * (ej + R(1.5) * (eXe - trX * R(1.0 / 3.0)));
-        // static part w^p_i p0 - s_i in FP64, then the gradient terms
-        v += R((axis ? c.wp_ax_d : c.wp_off_d) * p0 - c.shift[i]);
-        v -= (axis ? c.wt_ax : c.wt_off) * klap;
-        if (WITH_M) {
-            R m = R(0);
-#pragma unroll
-            for (int a = 0; a < DIM; a++) {
-                const bool touches = ecomp<L>(i, a) != 0;
-                R wa = axis ? (touches ? c.wm_para : c.wm_perp) : (touches ? c.wm_in : c.wm_out);
-                m += wa * M[a];
-            }
-            // off-diagonal weights e_a e_b / 4 (constraint list after Eq. (fi))
-            if (e0 * e1 != 0) m += R(0.25 * e0 * e1) * Mxy;
-            if (e1 * e2 != 0) m += R(0.25 * e1 * e2) * Myz;
-            if (e2 * e0 != 0) m += R(0.25 * e2 * e0) * Mzx;
-            v += m;
-        }
-        feq[i] = v;
-        sum += v;
+        if (opp<L>(i) < i) continue;
+        R even, odd;
+        eq_pair<L, WITH_M>(c, s, i, j, d, even, odd);
+        feq[i] = even + odd;
+        feq[opp<L>(i)] = even - odd;
+        sum += even;
     }
-    feq[0] = rho_dev - sum;
-    return rho;
+    feq[0] = rho_dev - R(2) * sum;
+    return s.rho;
 }
 
-// Forcing term of Section "Using a forcing method":
-// F_i = w_i [e.g + (3/2)(e_a e_b - delta_ab/3)(u_a g_b + u_b g_a)], i >= 1,
-// and F_0 = -sum_{i>=1} F_i (zero mass source).
+// Forcing term F_i of section "Using a forcing method" split like eq_pair:
+// even part w_i (3 (e_i.u)(e_i.g) - u.g), odd part w_i e_i.g.
+template <class L, class R>
+__device__ __forceinline__ void force_pair(const Coefs<R> &c, int i, const R u[3], const R g[3], R ug, R &even,
+                                           R &odd)
+{
+    const int e0 = L::ex[i], e1 = L::ey[i], e2 = L::ez[i];
+    R eu = R(e0) * u[0] + R(e1) * u[1] + R(e2) * u[2];
+    R eg = R(e0) * g[0] + R(e1) * g[1] + R(e2) * g[2];
+    R w = nnz<L>(i) == 1 ? c.w_ax : c.w_off;
+    // (3/2)(2 (e.u)(e.g) - (2/3) u.g)
+    even = w * (R(3) * eu * eg - ug);
+    odd = w * eg;
+}
+
+// BGK collision of Eq. (latbolt) with the forcing term when FORCE: out_i =
+// f_i + omega (f_i^eq - f_i) + F_i for the populations fin (deviations from
+// the shift), the equilibrium and forcing terms evaluated per pair of
+// opposite velocities.  g: body force (FORCE only).  Returns the site
+// quantities (rho, u) for the caller's observables.
+template <class L, bool FORCE, class R>
+__device__ __forceinline__ EqSite<R> collide(const Coefs<R> &c, R rho_dev, const R j[3], const R d[3], R lap,
+                                             const R g[3], const R fin[L::Q], R out[L::Q])
+{
+    const EqSite<R> s = eq_site<L, !FORCE>(c, rho_dev, j, d, lap);
+    const R ug = FORCE ? s.u[0] * g[0] + s.u[1] * g[1] + s.u[2] * g[2] : R(0);
+    R sum = R(0), fsum = R(0);
+#pragma unroll
+    for (int i = 1; i < L::Q; i++) {
+        if (opp<L>(i) < i) continue;
+        const int o = opp<L>(i);
+        R even, odd;
+        eq_pair<L, !FORCE>(c, s, i, j, d, even, odd);
+        sum += even;
+        R fi = fin[i], fo = fin[o];
+        out[i] = fi + c.omega * (even + odd - fi);
+        out[o] = fo + c.omega * (even - odd - fo);
+        if (FORCE) {
+            R fe, fd;
+            force_pair<L>(c, i, s.u, g, ug, fe, fd);
+            fsum += fe;
+            out[i] += fe + fd;
+            out[o] += fe - fd;
+        }
+    }
+    const R f0 = fin[0];
+    out[0] = f0 + c.omega * (rho_dev - R(2) * sum - f0);
+    if (FORCE) out[0] += R(-2) * fsum;
+    return s;
+}
+
 template <class L, class R>
 __device__ __forceinline__ void forcing(const Coefs<R> &c, const R u[3], const R g[3], R F[L::Q])
 {
@@ -171,16 +271,14 @@ __device__ __forceinline__ void forcing(const Coefs<R> &c, const R u[3], const R
     R sum = R(0);
 #pragma unroll
     for (int i = 1; i < L::Q; i++) {
-        const int e0 = L::ex[i], e1 = L::ey[i], e2 = L::ez[i];
-        R eu = R(e0) * u[0] + R(e1) * u[1] + R(e2) * u[2];
-        R eg = R(e0) * g[0] + R(e1) * g[1] + R(e2) * g[2];
-        R w = nnz<L>(i) == 1 ? c.w_ax : c.w_off;
-        // (3/2)(2 (e.u)(e.g) - (2/3) u.g)
-        R v = w * (eg + R(3) * eu * eg - ug);
-        F[i] = v;
-        sum += v;
+        if (opp<L>(i) < i) continue;
+        R even, odd;
+        force_pair<L>(c, i, u, g, ug, even, odd);
+        F[i] = even + odd;
+        F[opp<L>(i)] = even - odd;
+        sum += even;
     }
-    F[0] = -sum;
+    F[0] = R(-2) * sum;
 }
 
 __device__ __forceinline__ int wrap1(int v, int n)

@@ -119,7 +119,16 @@ __device__ __forceinline__ void step_tile(const Job<R> &J, const Coefs<R> &c)
     constexpr unsigned ES = sizeof(S);
 
     __shared__ R rho_s[NR * PL];
-    __shared__ R grad_s[FORCE ? 3 * 3 * GPL : 1];
+    // Gradient ring (forcing scheme): per site of the tile + 1 ring, the
+    // gradient of rho and, in FP32, the tensor T_ab = kappa (d_a d_b -
+    // delta_ab |d|^2 / 2) whose stencil divergence is the body force (3D:
+    // xx, yy, zz, xy, xz, yz; 2D: xx, xy, as T_yy = -T_xx).  Precomputing T
+    // once per ring site replaces the per-neighbour products of the force
+    // sum; in FP64 the ring would not fit the LDS, so T is formed there on
+    // the fly from the stored gradient.
+    constexpr bool TT = FORCE && sizeof(R) == 4;
+    constexpr int NG = TT ? (L::DIM == 3 ? 9 : 4) : 3;
+    __shared__ R grad_s[FORCE ? 3 * NG * GPL : 1];
 
     const S *src = static_cast<const S *>(J.src);
     S *dst = static_cast<S *>(J.dst);
@@ -233,24 +242,54 @@ __device__ __forceinline__ void step_tile(const Job<R> &J, const Coefs<R> &c)
 
     // gradient of rho on the tile + 1 ring of local plane lp (forcing only)
     auto grad_at = [&](int lp, int comp, int lx, int ly) -> R & {
-        return grad_s[((lp % 3) * 3 + comp) * GPL + ly * TXG + lx];
+        return grad_s[((lp % 3) * NG + comp) * GPL + ly * TXG + lx];
+    };
+    // component index of T_ab in the ring (TT only); 2D T_yy is -T_xx
+    auto t_comp = [](int a, int b) constexpr -> int {
+        if (L::DIM == 2) return a == b ? 2 : 3;
+        if (a == b) return 3 + a;
+        const int lo = a < b ? a : b, hi = a < b ? b : a;
+        return lo == 0 ? (hi == 1 ? 6 : 7) : 8;
+    };
+    auto t_at = [&](int lp, int a, int b, int lx, int ly) -> R {
+        const R v = grad_at(lp, t_comp(a, b), lx, ly);
+        return (L::DIM == 2 && a == 1 && b == 1) ? -v : v;
+    };
+    // stencil gradient of the density plane ring at local site (rx, ry) of
+    // local plane lp, summed per weight class: d_a = A sum_axis e_a rho +
+    // B sum_off e_a rho
+    auto gradient = [&](int lp, int rx, int ry, R(&d)[3]) {
+        R sa[3] = {R(0), R(0), R(0)}, so[3] = {R(0), R(0), R(0)};
+#pragma unroll
+        for (int i = 1; i < Q; i++) {
+            R r = rho_at(lp + op<L>(i), rx + ox<L>(i), ry + oy<L>(i));
+            R *acc = nnz<L>(i) == 1 ? sa : so;
+            if (L::ex[i]) acc[0] += R(L::ex[i]) * r;
+            if (L::ey[i]) acc[1] += R(L::ey[i]) * r;
+            if (L::ez[i]) acc[2] += R(L::ez[i]) * r;
+        }
+#pragma unroll
+        for (int a = 0; a < 3; a++) d[a] = c.A * sa[a] + c.B * so[a];
     };
     auto fill_grad = [&](int lp) {
         for (int k = tid; k < GPL; k += NT) {
             const int lx = k % TXG, ly = k / TXG;
             const int rx = lx + (H - 1), ry = ly + (HY - GY);
-            R d0 = R(0), d1 = R(0), d2 = R(0);
+            R d[3];
+            gradient(lp, rx, ry, d);
+            grad_at(lp, 0, lx, ly) = d[0];
+            grad_at(lp, 1, lx, ly) = d[1];
+            if (!TT || L::DIM == 3) grad_at(lp, 2, lx, ly) = d[2];
+            if constexpr (TT) {
+                const R h = R(0.5) * (d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
 #pragma unroll
-            for (int i = 1; i < Q; i++) {
-                R r = rho_at(lp + op<L>(i), rx + ox<L>(i), ry + oy<L>(i));
-                R cr = coef_grad<L>(c, i) * r;
-                if (L::ex[i]) d0 += R(L::ex[i]) * cr;
-                if (L::ey[i]) d1 += R(L::ey[i]) * cr;
-                if (L::ez[i]) d2 += R(L::ez[i]) * cr;
+                for (int a = 0; a < L::DIM; a++)
+#pragma unroll
+                    for (int b = a; b < L::DIM; b++) {
+                        if (L::DIM == 2 && a == 1 && b == 1) continue;
+                        grad_at(lp, t_comp(a, b), lx, ly) = c.kappa * (d[a] * d[b] - (a == b ? h : R(0)));
+                    }
             }
-            grad_at(lp, 0, lx, ly) = d0;
-            grad_at(lp, 1, lx, ly) = d1;
-            grad_at(lp, 2, lx, ly) = d2;
         }
     };
 
@@ -302,60 +341,57 @@ __device__ __forceinline__ void step_tile(const Job<R> &J, const Coefs<R> &c)
         for (int i = 1; i < Q; i++) {
             R r = rho_at(lc + op<L>(i), lx + ox<L>(i), ly + oy<L>(i));
             lap += coef_lap<L>(c, i) * (r - rho_dev);
-            if (!FORCE) {
-                R cr = coef_grad<L>(c, i) * r;
-                if (L::ex[i]) d[0] += R(L::ex[i]) * cr;
-                if (L::ey[i]) d[1] += R(L::ey[i]) * cr;
-                if (L::ez[i]) d[2] += R(L::ez[i]) * cr;
-            }
         }
+        if (!FORCE) gradient(lc, lx, ly, d);
         R g[3] = {R(0), R(0), R(0)};
         if (FORCE) {
             const int gx1 = tx + 1, gy1 = ty + GY;
             d[0] = grad_at(lc, 0, gx1, gy1);
             d[1] = grad_at(lc, 1, gx1, gy1);
-            d[2] = grad_at(lc, 2, gx1, gy1);
-            // g_a = -sum_i c_i kappa (dn_a (dn . e_i) - e_ia |dn|^2 / 2),
-            // dn the gradient at r + e_i: the divergence of the kappa part
-            // of the pressure tensor, Eq. (pt), with the force stencil
+            d[2] = L::DIM == 3 ? grad_at(lc, 2, gx1, gy1) : R(0);
+            // g_a = -sum_i c_i sum_b e_ib T_ab(r + e_i), T_ab = kappa (dn_a
+            // dn_b - delta_ab |dn|^2 / 2) with dn the gradient at r + e_i:
+            // the divergence of the kappa part of the pressure tensor,
+            // Eq. (pt), with the force stencil
 #pragma unroll
             for (int i = 1; i < Q; i++) {
                 int lp = lc + op<L>(i), qx = gx1 + ox<L>(i), qy = gy1 + oy<L>(i);
-                R n0 = grad_at(lp, 0, qx, qy), n1 = grad_at(lp, 1, qx, qy),
-                  n2 = grad_at(lp, 2, qx, qy);
-                R de = R(L::ex[i]) * n0 + R(L::ey[i]) * n1 + R(L::ez[i]) * n2;
-                R dd = R(0.5) * (n0 * n0 + n1 * n1 + n2 * n2);
                 R cf = coef_force<L>(c, i);
-                g[0] += cf * (n0 * de - R(L::ex[i]) * dd);
-                g[1] += cf * (n1 * de - R(L::ey[i]) * dd);
-                if (L::DIM == 3) g[2] += cf * (n2 * de - R(L::ez[i]) * dd);
+                if constexpr (TT) {
+#pragma unroll
+                    for (int a = 0; a < L::DIM; a++) {
+                        R t = R(0);
+#pragma unroll
+                        for (int b2 = 0; b2 < L::DIM; b2++)
+                            if (ecomp<L>(i, b2)) t += R(ecomp<L>(i, b2)) * t_at(lp, a, b2, qx, qy);
+                        g[a] += cf * t;
+                    }
+                } else {
+                    R n0 = grad_at(lp, 0, qx, qy), n1 = grad_at(lp, 1, qx, qy),
+                      n2 = grad_at(lp, 2, qx, qy);
+                    R de = R(L::ex[i]) * n0 + R(L::ey[i]) * n1 + R(L::ez[i]) * n2;
+                    R dd = R(0.5) * (n0 * n0 + n1 * n1 + n2 * n2);
+                    g[0] += cf * (n0 * de - R(L::ex[i]) * dd);
+                    g[1] += cf * (n1 * de - R(L::ey[i]) * dd);
+                    if (L::DIM == 3) g[2] += cf * (n2 * de - R(L::ez[i]) * dd);
+                }
             }
-            g[0] *= -c.kappa;
-            g[1] *= -c.kappa;
-            g[2] *= -c.kappa;
+            const R kg = TT ? R(-1) : -c.kappa;
+            g[0] *= kg;
+            g[1] *= kg;
+            g[2] *= kg;
         }
-        R feq[Q];
-        const R rho = equilibrium<L, !FORCE>(c, rho_dev, j, d, lap, feq);
-        R F[Q];
-        R inv_rho = R(1) / rho;
-        R u[3] = {j[0] * inv_rho, j[1] * inv_rho, j[2] * inv_rho};
-        if (FORCE) forcing<L>(c, u, g, F);
         const int p = wrapg(p0 + k, np);
         const unsigned site = unsigned(p * psz + Y[1] + X[1]);
         // collided populations (stored below)
         R out[Q];
-#pragma unroll
-        for (int i = 0; i < Q; i++) {
-            R dlt = fr[C0][i];
-            out[i] = dlt + c.omega * (feq[i] - dlt);
-            if (FORCE) out[i] += F[i];
-        }
+        const EqSite<R> es = collide<L, FORCE>(c, rho_dev, j, d, lap, g, fr[C0], out);
         if (own && J.observe) {
             J.obs_rho[site] = double(rho_dev) + c.shift_sum;
-            R h = FORCE ? R(0.5) * inv_rho : R(0);
-            J.obs_vel[site] = double(u[0] + h * g[0]);
-            J.obs_vel[J.obs_stride + site] = double(u[1] + h * g[1]);
-            J.obs_vel[2 * J.obs_stride + site] = double(L::DIM == 3 ? u[2] + h * g[2] : R(0));
+            R h = FORCE ? R(0.5) / es.rho : R(0);
+            J.obs_vel[site] = double(es.u[0] + h * g[0]);
+            J.obs_vel[J.obs_stride + site] = double(es.u[1] + h * g[1]);
+            J.obs_vel[2 * J.obs_stride + site] = double(L::DIM == 3 ? es.u[2] + h * g[2] : R(0));
         }
         // Densities of the next plane: its ring slot (plane lc+H+1) is read by
         // no thread in this iteration (ring depths 4 and 5), so no barrier is
