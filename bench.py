@@ -10,7 +10,9 @@ A step is one launch of the fused kernel over the whole lattice.
 Prints ONE JSON line: MLUPS (whole job), the dominant kernel's roofline
 (algorithmic bytes = 19 populations read + written = 152 B per site for
 FP32, over the average launch time from HIP events on the launch stream),
-and the FP64 CPU oracle timed on the host cores on a bounded sample.
+the batched time-to-steady of 512 held-out 128^2 drops from the cold start
+and from the shipped warm-start network (--no-batched skips it), and the
+FP64 CPU oracle timed on the host cores on a bounded sample.
 """
 import argparse
 import hashlib
@@ -128,6 +130,8 @@ def main():
     ap.add_argument("--planes", type=int, default=0)
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the batched time-to-steady leg (warm vs cold)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="instead: time a plain device copy of this many bytes (HBM counter "
                          "calibration for rocprofv3 --pmc)")
@@ -177,7 +181,7 @@ def main():
     achieved = bytes_site * n / (kern_ms * 1e-3) / 1e9
     traffic = measured_traffic(wl)
     out = {
-        "metric": "MLUPS (D3Q19 FP32 256^3 fused free-energy LBM step)",
+        "metric": "MLUPS and HBM GB/s (D3Q19 FP32 256^3); batched time-to-steady: warm vs cold",
         "value": round(mlups, 1),
         "unit": "MLUPS",
         "n_gpus": 1,
@@ -204,9 +208,15 @@ def main():
                      "kernel_ms": round(kern_ms, 5)},
         "state_after": {"finite": ok, "max_vel": vmax, "mass": mass, "momentum": mom},
     }
+    sim.close()
+    del sim
+    if not args.no_batched:
+        # second half of the metric: 512 held-out 128^2 drops (FP64 storage,
+        # residual 1e-10), cold start versus the shipped warm-start network
+        from paper_0710_5470_amd import warmstart
+        out["batched_time_to_steady"] = warmstart.time_to_steady()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl)
-    sim.close()
     print(json.dumps(out), flush=True)
 
 

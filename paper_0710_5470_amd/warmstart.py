@@ -15,6 +15,7 @@ torch only provides device memory and streams.  Training data are steady
 states that the batched runner itself produces.
 """
 import math
+import os
 import time
 
 import numpy as np
@@ -338,6 +339,28 @@ def evaluate(net, n_eval=512, side=128, seed=6, tol=1e-10, ref_tol=1e-13, ref_st
                          step_ratio_p90=float(np.percentile(ratio, 90)))
         _log("warm[%s]: %.2f s, %s" % (name, w["seconds"], out[name]))
     return out
+
+
+WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "warm_net_d2q9_128.npz")
+
+
+def time_to_steady(net=None, n=512, side=128, seed=6, tol=1e-10):
+    """Batched time-to-steady on held-out drops: the cold start, then the
+    default warm start (inference included), each to the residual `tol`.
+    Uses the shipped network when net is None."""
+    if net is None:
+        net = load_weights(WEIGHTS)
+    specs = inputs.stable_batch_specs(n, seed, side_lo=side, side_hi=side)
+    cold = steady_states(specs, side, tol)
+    warm = warm_start(net, specs, side, tol)
+    ok = lambda r: int((r["status"] == lbm.BATCH_CONVERGED).sum())
+    return dict(problems=n, side=side, tol=tol, seed=seed,
+                cold_seconds=round(cold["seconds"], 4), warm_seconds=round(warm["seconds"], 4),
+                warm_inference_seconds=round(warm["inference_seconds"], 4),
+                cold_steps=int(cold["steps"].sum()), warm_steps=int(warm["steps"].sum()),
+                cold_converged=ok(cold), warm_converged=ok(warm),
+                fallbacks=int(warm["fallback"].sum()),
+                speedup=round(cold["seconds"] / warm["seconds"], 4))
 
 
 def run_experiment(n_train=2048, n_eval=512, side=128, epochs=20, seed_train=5, seed_eval=6,
