@@ -271,7 +271,8 @@ int lbm_batch_destroy(lbm_batch *bt);
  * (like the lattice).  They run as implicit GEMMs on bf16 matrix cores with
  * FP32 accumulation: FP32 operands are rounded to bf16 (nearest even) as they
  * enter the MFMA.  Tensors are FP32, NHWC, 16-byte aligned, with padded
- * channel counts cin, cout in {16, 32}; nb * h * w must be a multiple of 16.
+ * channel counts cin, cout in {16, 32}; nb * h * w must be a multiple of 16
+ * and below 2^31.
  * Weights are [9][cout][cin] with tap 3 (dy + 1) + (dx + 1):
  *   out[p][co] = bias[co] + sum_{tap, ci} W[tap][co][ci] act(in[p + (dy, dx)][ci])
  * with act = max(., 0) when relu_in, else the identity.  Channels co >=

@@ -13,7 +13,7 @@ bool conv_ok(const lbm_conv_shape *s)
     if (s->cout < 16 || s->cout > 32 || s->cout % 16) return false;
     if (s->cout_real < 1 || s->cout_real > s->cout) return false;
     long long npix = (long long)s->nb * s->h * s->w;
-    return npix % 16 == 0;
+    return npix % 16 == 0 && npix <= 0x7FFFFFFFLL;  // 32-bit pixel indices in the kernels
 }
 
 lbmnet::ConvShape conv_shape(const lbm_conv_shape *s)
@@ -28,7 +28,8 @@ constexpr int NET_CHUNK = 1024;  // pixels per workgroup in the weight gradient
 unsigned conv_grid(const lbm_conv_shape *s)
 {
     long long npix = (long long)s->nb * s->h * s->w;
-    return unsigned((npix / 16 + 3) / 4);
+    const long long per_wg = 4LL * 16 * lbmnet::CONV_MT;  // 4 waves of CONV_MT 16-pixel tiles
+    return unsigned((npix + per_wg - 1) / per_wg);
 }
 
 } // namespace
@@ -58,7 +59,7 @@ size_t lbm_net_conv3x3_bwd_weight_workspace(const lbm_conv_shape *s)
     if (!conv_ok(s)) return 0;
     long long npix = (long long)s->nb * s->h * s->w;
     long long parts = (npix + NET_CHUNK - 1) / NET_CHUNK;
-    return size_t(parts) * 9 * s->cout * s->cin * sizeof(float);
+    return size_t(parts) * (9 * s->cout * s->cin + s->cout) * sizeof(float);
 }
 
 int lbm_net_conv3x3_bwd_weight(const lbm_conv_shape *s, const float *dev_dout, const float *dev_in,
@@ -73,9 +74,9 @@ int lbm_net_conv3x3_bwd_weight(const lbm_conv_shape *s, const float *dev_dout, c
     float *part = static_cast<float *>(dev_ws);
     lbmnet::conv_bwd_weight_kernel<<<parts, lbmnet::NET_THREADS, 0, st>>>(conv_shape(s), dev_dout, dev_in,
                                                                           relu_in, NET_CHUNK, part);
-    int len = 9 * s->cout * s->cin;
-    lbmnet::sum_parts_kernel<<<(len + 255) / 256, 256, 0, st>>>(parts, len, part, dev_dw);
-    lbmnet::bias_grad_kernel<<<s->cout, lbmnet::NET_THREADS, 0, st>>>(npix, s->cout, dev_dout, dev_db);
+    const int nw = 9 * s->cout * s->cin;
+    const int len = nw + s->cout;  // weight gradient, then bias gradient
+    lbmnet::sum_parts_kernel<<<(len + 63) / 64, 256, 0, st>>>(parts, len, nw, part, dev_dw, dev_db);
     return hipGetLastError() == hipSuccess ? LBM_OK : LBM_E_DEVICE;
 }
 
