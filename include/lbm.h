@@ -229,7 +229,9 @@ int lbm_batch_step(lbm_batch *bt, long long nsteps);
  * (patience <= 0 disables this), LBM_BATCH_NONFINITE on a bad
  * state, LBM_BATCH_MAXSTEPS when its step count reaches max_steps.
  * Per-problem outputs (host, may be NULL): steps taken while active, last
- * residual, status.  Synchronises once per K steps (4 bytes read back). */
+ * residual, status.  Synchronises once per K steps (4 bytes read back).
+ * While few problems remain active, work items march fewer planes (the
+ * caller's launch is restored on return); results do not depend on it. */
 int lbm_batch_run(lbm_batch *bt, double tol, int check_every, long long max_steps, int patience,
                   long long grace, long long *host_steps, double *host_residual, int *host_status);
 

@@ -111,6 +111,33 @@ int batch_items(lbm_batch *bt)
     return LBM_OK;
 }
 
+// Planes per work item while `active` problems remain.  A step's latency is
+// one work item's plane march, so when few problems are left the march is
+// shortened (halving from cp0, not below LBM_TAIL_MIN_PLANES) until there
+// are again LBM_TAIL_ITEMS_PER_CU work items per compute unit.  Results do not depend on the launch.
+#ifndef LBM_TAIL_ITEMS_PER_CU
+#define LBM_TAIL_ITEMS_PER_CU 2
+#endif
+#ifndef LBM_TAIL_MIN_PLANES
+#define LBM_TAIL_MIN_PLANES 4
+#endif
+
+int tail_planes(const lbm_batch *bt, int active, int cp0)
+{
+    const TileShape t = tile_shape(bt->base.lattice, bt->tile);
+    double tiles = 0.0, planes = 0.0;
+    for (int k = 0; k < bt->nprob; k++) {
+        tiles += double((bt->gnx[k] + t.tx - 1) / t.tx) * ((bt->gny[k] + t.ty - 1) / t.ty);
+        planes += bt->gnp[k];
+    }
+    tiles /= bt->nprob;
+    planes /= bt->nprob;
+    const double target = double(LBM_TAIL_ITEMS_PER_CU) * std::max(1, bt->cus);
+    int cp = cp0;
+    while (cp > LBM_TAIL_MIN_PLANES && active * tiles * std::ceil(planes / cp) < target) cp /= 2;
+    return cp;
+}
+
 template <class L, int SCH, class S, class R, int TX, int TY>
 void batch_launch_one(lbm_batch *bt, const BatchArgs<R> &a)
 {
@@ -380,7 +407,15 @@ int lbm_batch_run(lbm_batch *bt, double tol, int check_every, long long max_step
     int *count = bptr<int>(bt, bt->o_count);
     int h_count = bt->nprob;
     long long done = 0;
+    const int cp0 = bt->cp;
     while (h_count > 0 && done < max_steps) {
+        const int cp = tail_planes(bt, h_count, cp0);
+        if (cp != bt->cp) {
+            bt->cp = cp;
+            if ((rc = batch_items(bt)) != LBM_OK ||
+                (rc = batch_capture(bt, K, tol, patience, grace, max_steps)) != LBM_OK)
+                return rc;
+        }
         if (hipGraphLaunch(bt->exec, bt->stream) != hipSuccess) return LBM_E_DEVICE;
         done += K;
         if (hipMemcpyAsync(&h_count, count, sizeof(int), hipMemcpyDeviceToHost, bt->stream) != hipSuccess ||
@@ -388,6 +423,10 @@ int lbm_batch_run(lbm_batch *bt, double tol, int check_every, long long max_step
             return LBM_E_DEVICE;
     }
     bt->steps += done;
+    if (bt->cp != cp0) {  // the caller's launch again for later calls
+        bt->cp = cp0;
+        if ((rc = batch_items(bt)) != LBM_OK) return rc;
+    }
     std::vector<BatchState> st(bt->nprob);
     if (hipMemcpyAsync(st.data(), bptr<BatchState>(bt, bt->o_state), st.size() * sizeof(BatchState),
                        hipMemcpyDeviceToHost, bt->stream) != hipSuccess ||
