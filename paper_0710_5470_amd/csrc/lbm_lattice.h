@@ -264,23 +264,6 @@ __device__ __forceinline__ EqSite<R> collide(const Coefs<R> &c, R rho_dev, const
     return s;
 }
 
-template <class L, class R>
-__device__ __forceinline__ void forcing(const Coefs<R> &c, const R u[3], const R g[3], R F[L::Q])
-{
-    R ug = u[0] * g[0] + u[1] * g[1] + u[2] * g[2];
-    R sum = R(0);
-#pragma unroll
-    for (int i = 1; i < L::Q; i++) {
-        if (opp<L>(i) < i) continue;
-        R even, odd;
-        force_pair<L>(c, i, u, g, ug, even, odd);
-        F[i] = even + odd;
-        F[opp<L>(i)] = even - odd;
-        sum += even;
-    }
-    F[0] = R(-2) * sum;
-}
-
 __device__ __forceinline__ int wrap1(int v, int n)
 {
     // v in [-1, n]

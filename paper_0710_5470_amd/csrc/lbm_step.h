@@ -95,7 +95,6 @@ template <class R> struct Job {
     double *obs_vel;       // component a at obs_vel + a * obs_stride
     long long obs_stride;
     int nx, ny, np;        // in-plane x, in-plane y (1 for D2Q9), planes
-    int n;                 // sites of this problem
     int x0, y0, p0, npl;
     int write_pops, observe;
 };
@@ -456,7 +455,6 @@ void step_kernel(StepArgs<R> A)
     J.nx = A.nx;
     J.ny = A.ny;
     J.np = A.np;
-    J.n = int(A.n);
     J.x0 = tile_x * TX;
     J.y0 = tile_y * TY;
     J.p0 = chunk * A.cp;
@@ -519,7 +517,6 @@ void batch_step_kernel(BatchArgs<R> B)
         J.nx = P.nx;
         J.ny = P.ny;
         J.np = P.np;
-        J.n = P.nx * P.ny * P.np;
         J.x0 = tile_x * TX;
         J.y0 = tile_y * TY;
         J.p0 = chunk * P.cp;
