@@ -84,6 +84,18 @@ __device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, unsigned vof
 #define LBM_STEP_WAVES_PER_EU 1
 #endif
 
+// Planes ahead of the density front at which the forcing scheme loads its
+// halo populations: 1, 2, or 0 = 2 for FP64 storage and 1 for FP32.
+// Own-site loads (from HBM) are always one plane ahead and issued first;
+// with 2, the halo loads (mostly L2 hits) for the plane after next go out
+// behind them, so the wait for the own loads leaves them in flight.  This
+// costs 19 registers and a load from every thread, also those without a
+// halo site: it pays for FP64 populations (D3Q19 256^3: 1.626 against
+// 1.688 ms per step) and not for FP32 (0.747 against 0.684 ms).
+#ifndef LBM_HALO_AHEAD
+#define LBM_HALO_AHEAD 0
+#endif
+
 // One workgroup's share of a step: the tile at (x0, y0) of planes
 // [p0, p0 + npl) of one problem.
 template <class R> struct Job {
@@ -190,9 +202,11 @@ __device__ __forceinline__ void step_tile(const Job<R> &J, const Coefs<R> &c)
     // for k = 0..H; fr[H + 1] receives the next plane, whose loads are in
     // flight while the current plane is collided (software pipelining: the
     // memory latency of plane p + H + 1 overlaps the arithmetic of plane p).
-    // hr holds the in-flight halo populations of that next plane.
+    // hr holds the in-flight halo populations, HA planes deep.
+    constexpr int HA =
+        FORCE && (LBM_HALO_AHEAD == 2 || (LBM_HALO_AHEAD == 0 && sizeof(S) == 8)) ? 2 : 1;
     R fr[H + 2][Q];
-    R hr[NHT][Q];
+    R hr[HA][NHT][Q];
 
     // issue the Q loads of the populations arriving at the site with offsets
     // (Xo, Yo) in the plane whose wrapped neighbour-plane offsets are P
@@ -222,21 +236,28 @@ __device__ __forceinline__ void step_tile(const Job<R> &J, const Coefs<R> &c)
     };
 
     // local plane lp is global plane p0 - H + lp: issue the loads of its own
-    // site (into f) and halo sites (into hr), then store their densities
-    auto load_plane = [&](int lp, R(&f)[Q]) {
+    // site (into f) or of its halo sites (into h); store their densities
+    auto load_own = [&](int lp, R(&f)[Q]) {
         int P[3];
         plane_offsets(wrapg(p0 - H + lp, np), P);
         pull(X, Y, P, f);
+    };
+    auto load_halo = [&](int lp, R(&h)[NHT][Q]) {
+        int P[3];
+        plane_offsets(wrapg(p0 - H + lp, np), P);
+        // With HA = 2 threads without a halo site load a valid dummy site
+        // (lx = ly = 0) and ignore it: without a branch the compiler can
+        // count these loads and leave them in flight at the next wait.
 #pragma unroll
         for (int s = 0; s < NHT; s++)
-            if (hv[s]) pull(hX[s], hY[s], P, hr[s]);
+            if (HA == 2 || hv[s]) pull(hX[s], hY[s], P, h[s]);
     };
-    auto store_rho = [&](int lp, const R(&f)[Q]) {
+    auto store_rho = [&](int lp, const R(&f)[Q], const R(&h)[NHT][Q]) {
         R *ring = rho_s + (lp % NR) * PL;
         ring[(ty + HY) * TXH + tx + H] = dens(f);
 #pragma unroll
         for (int s = 0; s < NHT; s++)
-            if (hv[s]) ring[hL[s]] = dens(hr[s]);
+            if (hv[s]) ring[hL[s]] = dens(h[s]);
     };
 
     // gradient of rho on the tile + 1 ring of local plane lp (forcing only)
@@ -295,14 +316,18 @@ __device__ __forceinline__ void step_tile(const Job<R> &J, const Coefs<R> &c)
     // prologue: densities of planes p0-H .. p0+H (own populations of
     // p0 .. p0+H kept in fr[0..H]), gradients of p0-1, p0
     for (int lp = 0; lp < H; lp++) {
-        load_plane(lp, fr[H + 1]);
-        store_rho(lp, fr[H + 1]);
+        load_own(lp, fr[H + 1]);
+        load_halo(lp, hr[0]);
+        store_rho(lp, fr[H + 1], hr[0]);
     }
 #pragma unroll
     for (int s = 0; s <= H; s++) {
-        load_plane(H + s, fr[s]);
-        store_rho(H + s, fr[s]);
+        load_own(H + s, fr[s]);
+        load_halo(H + s, hr[0]);
+        store_rho(H + s, fr[s], hr[0]);
     }
+    // with HA = 2 the halo of plane 2H + 1 (the first front) is loaded here
+    if (HA == 2 && npl > 1) load_halo(2 * H + 1, hr[0]);
     __syncthreads();
     if (FORCE) {
         fill_grad(1);
@@ -317,9 +342,13 @@ __device__ __forceinline__ void step_tile(const Job<R> &J, const Coefs<R> &c)
         constexpr int RING = H + 2;
         constexpr int C0 = decltype(phase)::value % RING;            // plane lc
         constexpr int CN = (decltype(phase)::value + H + 1) % RING;  // plane lc + H + 1
+        constexpr int HB = decltype(phase)::value % HA;               // halo of plane lc + H + 1
+        constexpr int HN = (decltype(phase)::value + 1) % HA;         // halo of plane lc + H + HA
         const int lc = H + k;  // local index of the plane collided now
         const bool more = decltype(always_more)::value || k + 1 < npl;
-        if (more) load_plane(lc + H + 1, fr[CN]);  // consumed after the collision
+        const bool more_h = decltype(always_more)::value || k + HA < npl;
+        if (more) load_own(lc + H + 1, fr[CN]);  // consumed after the collision
+        if (more_h) load_halo(lc + H + HA, hr[HN]);
         __syncthreads();  // densities up to plane lc + H are in LDS
         if (FORCE) {
             fill_grad(lc + 1);
@@ -397,7 +426,7 @@ __device__ __forceinline__ void step_tile(const Job<R> &J, const Coefs<R> &c)
         // needed before this store; the next iteration's first barrier
         // publishes it.  The next gradient fill overwrites a plane read above
         // only after that barrier.
-        if (more) store_rho(lc + H + 1, fr[CN]);
+        if (more) store_rho(lc + H + 1, fr[CN], hr[HB]);
         // Global stores after the wait for the prefetched loads: memory
         // counters retire in order, so a wait on a load issued before these
         // stores would also wait for their write acknowledgements.
@@ -412,22 +441,27 @@ __device__ __forceinline__ void step_tile(const Job<R> &J, const Coefs<R> &c)
     // counting knows that the register ring is complete at the loop head (a
     // runtime prefetch condition made it wait for the fresh loads before the
     // collision).  The last group checks the condition at run time.
+    // (The halo double buffer alternates with the plane parity, which the
+    // ring phase keeps because the ring has H + 2 = 4 slots when HA = 2.)
+    static_assert(HA == 1 || (H + 2) % 2 == 0, "halo buffer parity follows the ring phase");
     using P0 = std::integral_constant<int, 0>;
     using P1 = std::integral_constant<int, 1>;
     using P2 = std::integral_constant<int, 2>;
     using P3 = std::integral_constant<int, 3>;
     int k = 0;
-    for (; k + H + 2 < npl; k += H + 2) {
+    for (; k + H + 1 + HA < npl; k += H + 2) {
         iteration(k, P0{}, std::true_type{});
         iteration(k + 1, P1{}, std::true_type{});
         iteration(k + 2, P2{}, std::true_type{});
         if constexpr (H == 2) iteration(k + 3, P3{}, std::true_type{});
     }
-    iteration(k, P0{}, std::false_type{});
-    if (k + 1 < npl) iteration(k + 1, P1{}, std::false_type{});
-    if (k + 2 < npl) iteration(k + 2, P2{}, std::false_type{});
-    if constexpr (H == 2) {
-        if (k + 3 < npl) iteration(k + 3, P3{}, std::false_type{});
+    for (; k < npl; k += H + 2) {
+        iteration(k, P0{}, std::false_type{});
+        if (k + 1 < npl) iteration(k + 1, P1{}, std::false_type{});
+        if (k + 2 < npl) iteration(k + 2, P2{}, std::false_type{});
+        if constexpr (H == 2) {
+            if (k + 3 < npl) iteration(k + 3, P3{}, std::false_type{});
+        }
     }
 }
 
