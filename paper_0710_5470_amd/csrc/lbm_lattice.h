@@ -47,6 +47,29 @@ template <class L> __host__ __device__ constexpr int ecomp(int i, int a)
 {
     return a == 0 ? L::ex[i] : (a == 1 ? L::ey[i] : L::ez[i]);
 }
+// e_i . v summed over the nonzero components of e_i only.  Under IEEE rules
+// the compiler may not drop a product with a zero component (0 * inf is
+// NaN), so the plain three-term form costs a multiply-add per zero
+// component.  With at most two nonzero components of +-1 (D2Q9, D3Q19) the
+// result is the single rounding of the full dot product.
+template <class L, class R> __device__ __forceinline__ R edot(int i, const R v[3])
+{
+    R s = R(0);
+    bool any = false;
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        const int e = ecomp<L>(i, a);
+        if (e == 0) continue;
+        const R t = e > 0 ? v[a] : -v[a];
+        s = any ? s + t : t;
+        any = true;
+    }
+    return s;
+}
+// Start value of a sum that the compiler can fold into its first term:
+// -0 + x is x for every x, whereas +0 + x is not when x is -0.
+template <class R> __device__ __forceinline__ constexpr R sum0() { return R(-0.0); }
+
 // the velocity opposite to e_i
 template <class L> __host__ __device__ constexpr int opp(int i)
 {
@@ -161,9 +184,9 @@ __device__ __forceinline__ void eq_pair(const Coefs<R> &c, const EqSite<R> &s, i
 {
     const int e0 = L::ex[i], e1 = L::ey[i], e2 = L::ez[i];
     const bool axis = nnz<L>(i) == 1;
-    R eu = R(e0) * s.u[0] + R(e1) * s.u[1] + R(e2) * s.u[2];
-    R ed = R(e0) * d[0] + R(e1) * d[1] + R(e2) * d[2];
-    R ej = R(e0) * j[0] + R(e1) * j[1] + R(e2) * j[2];
+    R eu = edot<L>(i, s.u);
+    R ed = edot<L>(i, d);
+    R ej = edot<L>(i, j);
     R ee = R(nnz<L>(i));
     // sum_ab (e_a e_b - delta_ab / 3) X_ab
     R eXe = s.rho * eu * eu + s.lam * (R(2) * eu * ed + ee * s.ud);
@@ -171,7 +194,7 @@ __device__ __forceinline__ void eq_pair(const Coefs<R> &c, const EqSite<R> &s, i
     R v = (axis ? s.st_ax : s.st_off) + w * R(1.5) * (eXe - s.trX3);
     v -= (axis ? c.wt_ax : c.wt_off) * s.klap;
     if (WITH_M) {
-        R m = R(0);
+        R m = sum0<R>();
 #pragma unroll
         for (int a = 0; a < L::DIM; a++) {
             const bool touches = ecomp<L>(i, a) != 0;
@@ -219,9 +242,8 @@ template <class L, class R>
 __device__ __forceinline__ void force_pair(const Coefs<R> &c, int i, const R u[3], const R g[3], R ug, R &even,
                                            R &odd)
 {
-    const int e0 = L::ex[i], e1 = L::ey[i], e2 = L::ez[i];
-    R eu = R(e0) * u[0] + R(e1) * u[1] + R(e2) * u[2];
-    R eg = R(e0) * g[0] + R(e1) * g[1] + R(e2) * g[2];
+    R eu = edot<L>(i, u);
+    R eg = edot<L>(i, g);
     R w = nnz<L>(i) == 1 ? c.w_ax : c.w_off;
     // (3/2)(2 (e.u)(e.g) - (2/3) u.g)
     even = w * (R(3) * eu * eg - ug);
@@ -238,8 +260,8 @@ __device__ __forceinline__ EqSite<R> collide(const Coefs<R> &c, R rho_dev, const
                                              const R g[3], const R fin[L::Q], R out[L::Q])
 {
     const EqSite<R> s = eq_site<L, !FORCE>(c, rho_dev, j, d, lap);
-    const R ug = FORCE ? s.u[0] * g[0] + s.u[1] * g[1] + s.u[2] * g[2] : R(0);
-    R sum = R(0), fsum = R(0);
+    const R ug = FORCE ? s.u[0] * g[0] + s.u[1] * g[1] + (L::DIM == 3 ? s.u[2] * g[2] : R(0)) : R(0);
+    R sum = sum0<R>(), fsum = sum0<R>();
 #pragma unroll
     for (int i = 1; i < L::Q; i++) {
         if (opp<L>(i) < i) continue;

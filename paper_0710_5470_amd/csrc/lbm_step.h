@@ -219,7 +219,7 @@ __device__ __forceinline__ void step_tile(const Job<R> &J, const Coefs<R> &c)
     };
     // rho - sum_i s_i of pulled populations (fixed summation order)
     auto dens = [&](const R(&f)[Q]) -> R {
-        R s = R(0);
+        R s = sum0<R>();
 #pragma unroll
         for (int i = 0; i < Q; i++) s += f[i];
         return s;
@@ -279,7 +279,7 @@ __device__ __forceinline__ void step_tile(const Job<R> &J, const Coefs<R> &c)
     // local plane lp, summed per weight class: d_a = A sum_axis e_a rho +
     // B sum_off e_a rho
     auto gradient = [&](int lp, int rx, int ry, R(&d)[3]) {
-        R sa[3] = {R(0), R(0), R(0)}, so[3] = {R(0), R(0), R(0)};
+        R sa[3] = {sum0<R>(), sum0<R>(), sum0<R>()}, so[3] = {sum0<R>(), sum0<R>(), sum0<R>()};
 #pragma unroll
         for (int i = 1; i < Q; i++) {
             R r = rho_at(lp + op<L>(i), rx + ox<L>(i), ry + oy<L>(i));
@@ -289,7 +289,7 @@ __device__ __forceinline__ void step_tile(const Job<R> &J, const Coefs<R> &c)
             if (L::ez[i]) acc[2] += R(L::ez[i]) * r;
         }
 #pragma unroll
-        for (int a = 0; a < 3; a++) d[a] = c.A * sa[a] + c.B * so[a];
+        for (int a = 0; a < 3; a++) d[a] = a < L::DIM ? c.A * sa[a] + c.B * so[a] : R(0);
     };
     auto fill_grad = [&](int lp) {
         for (int k = tid; k < GPL; k += NT) {
@@ -301,7 +301,7 @@ __device__ __forceinline__ void step_tile(const Job<R> &J, const Coefs<R> &c)
             grad_at(lp, 1, lx, ly) = d[1];
             if (!TT || L::DIM == 3) grad_at(lp, 2, lx, ly) = d[2];
             if constexpr (TT) {
-                const R h = R(0.5) * (d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+                const R h = R(0.5) * (d[0] * d[0] + d[1] * d[1] + (L::DIM == 3 ? d[2] * d[2] : R(0)));
 #pragma unroll
                 for (int a = 0; a < L::DIM; a++)
 #pragma unroll
@@ -356,7 +356,7 @@ __device__ __forceinline__ void step_tile(const Job<R> &J, const Coefs<R> &c)
         }
         const int lx = tx + H, ly = ty + HY;
         const R rho_dev = rho_at(lc, lx, ly);
-        R j[3] = {R(0), R(0), R(0)};
+        R j[3] = {sum0<R>(), sum0<R>(), L::DIM == 3 ? sum0<R>() : R(0)};
 #pragma unroll
         for (int i = 1; i < Q; i++) {
             if (L::ex[i]) j[0] += R(L::ex[i]) * fr[C0][i];
@@ -364,7 +364,7 @@ __device__ __forceinline__ void step_tile(const Job<R> &J, const Coefs<R> &c)
             if (L::ez[i]) j[2] += R(L::ez[i]) * fr[C0][i];
         }
         R d[3] = {R(0), R(0), R(0)};
-        R lap = R(0);
+        R lap = sum0<R>();
 #pragma unroll
         for (int i = 1; i < Q; i++) {
             R r = rho_at(lc + op<L>(i), lx + ox<L>(i), ly + oy<L>(i));
@@ -381,27 +381,42 @@ __device__ __forceinline__ void step_tile(const Job<R> &J, const Coefs<R> &c)
             // dn_b - delta_ab |dn|^2 / 2) with dn the gradient at r + e_i:
             // the divergence of the kappa part of the pressure tensor,
             // Eq. (pt), with the force stencil
+            if constexpr (TT) {
+                // the T terms summed per weight class (one coefficient each),
+                // then scaled
+                R ga[2][3];
 #pragma unroll
-            for (int i = 1; i < Q; i++) {
-                int lp = lc + op<L>(i), qx = gx1 + ox<L>(i), qy = gy1 + oy<L>(i);
-                R cf = coef_force<L>(c, i);
-                if constexpr (TT) {
+                for (int a = 0; a < 3; a++) ga[0][a] = ga[1][a] = sum0<R>();
 #pragma unroll
-                    for (int a = 0; a < L::DIM; a++) {
-                        R t = R(0);
+                for (int i = 1; i < Q; i++) {
+                    const int lp = lc + op<L>(i), qx = gx1 + ox<L>(i), qy = gy1 + oy<L>(i);
+                    R *acc = nnz<L>(i) == 1 ? ga[0] : ga[1];
+#pragma unroll
+                    for (int a = 0; a < L::DIM; a++)
 #pragma unroll
                         for (int b2 = 0; b2 < L::DIM; b2++)
-                            if (ecomp<L>(i, b2)) t += R(ecomp<L>(i, b2)) * t_at(lp, a, b2, qx, qy);
+                            if (ecomp<L>(i, b2)) acc[a] += R(ecomp<L>(i, b2)) * t_at(lp, a, b2, qx, qy);
+                }
+#pragma unroll
+                for (int a = 0; a < L::DIM; a++) g[a] = c.Ef * ga[0][a] + c.Ff * ga[1][a];
+            } else {
+#pragma unroll
+                for (int a = 0; a < L::DIM; a++) g[a] = sum0<R>();
+#pragma unroll
+                for (int i = 1; i < Q; i++) {
+                    const int lp = lc + op<L>(i), qx = gx1 + ox<L>(i), qy = gy1 + oy<L>(i);
+                    const R cf = coef_force<L>(c, i);
+                    R n[3] = {grad_at(lp, 0, qx, qy), grad_at(lp, 1, qx, qy),
+                              L::DIM == 3 ? grad_at(lp, 2, qx, qy) : R(0)};
+                    R de = edot<L>(i, n);
+                    R dd = R(0.5) * (n[0] * n[0] + n[1] * n[1] + (L::DIM == 3 ? n[2] * n[2] : R(0)));
+#pragma unroll
+                    for (int a = 0; a < L::DIM; a++) {
+                        // n_a (e.n) - e_a |n|^2 / 2, one fused rounding
+                        const int e = ecomp<L>(i, a);
+                        const R t = e > 0 ? n[a] * de - dd : (e < 0 ? n[a] * de + dd : n[a] * de);
                         g[a] += cf * t;
                     }
-                } else {
-                    R n0 = grad_at(lp, 0, qx, qy), n1 = grad_at(lp, 1, qx, qy),
-                      n2 = grad_at(lp, 2, qx, qy);
-                    R de = R(L::ex[i]) * n0 + R(L::ey[i]) * n1 + R(L::ez[i]) * n2;
-                    R dd = R(0.5) * (n0 * n0 + n1 * n1 + n2 * n2);
-                    g[0] += cf * (n0 * de - R(L::ex[i]) * dd);
-                    g[1] += cf * (n1 * de - R(L::ey[i]) * dd);
-                    if (L::DIM == 3) g[2] += cf * (n2 * de - R(L::ez[i]) * dd);
                 }
             }
             const R kg = TT ? R(-1) : -c.kappa;
