@@ -136,10 +136,20 @@ template <class R> __device__ __forceinline__ void vdw(const Coefs<R> &c, double
 // Site quantities the equilibrium of Eq. (equilibrium) needs for every
 // direction.  rho_dev = rho - sum_i s_i (rho itself when s = 0); j:
 // momentum; d: discrete gradient of rho; lap: discrete Laplacian.
+//
+// Per direction the second-moment term is (3/2) w_i sum_ab (e_ia e_ib -
+// delta_ab / 3) X_ab with X_ab = rho u_a u_b + lam (u_a d_b + u_b d_a +
+// delta_ab u.d); its contraction with e_i e_i is
+//   (e.u) (rho e.u + 2 lam e.d) + lam |e|^2 u.d,
+// and the terms that depend on the direction only through its weight class
+// (w^p_i p0 - s_i, the trace part, -w^t_i kappa rho lap) are summed once per
+// class into stc.
 template <class R> struct EqSite {
-    R rho, u[3], lam, ud, trX3, klap;
+    R rho, u[3];
+    R lam2;                 // 2 lam
+    R lud[2];               // lam |e|^2 u.d for |e|^2 = 1, 2
+    R stc[2];               // class terms, axis and off-axis
     R M[3], Mxy, Myz, Mzx;  // kappa d_a rho d_b rho (equilibrium scheme)
-    R st_ax, st_off;        // static part w^p_i p0 - s_i per weight class
 };
 
 template <class L, bool WITH_M, class R>
@@ -155,12 +165,15 @@ __device__ __forceinline__ EqSite<R> eq_site(const Coefs<R> &c, R rho_dev, const
     s.u[2] = DIM == 3 ? j[2] * inv_rho : R(0);
     double p0, cs2;
     vdw(c, rho_d, p0, cs2);
-    s.lam = c.lambda_on ? R(c.nu * (1.0 - 3.0 * cs2)) : R(0);
-    s.ud = s.u[0] * d[0] + s.u[1] * d[1] + (DIM == 3 ? s.u[2] * d[2] : R(0));
+    const R lam = c.lambda_on ? R(c.nu * (1.0 - 3.0 * cs2)) : R(0);
+    const R ud = s.u[0] * d[0] + s.u[1] * d[1] + (DIM == 3 ? s.u[2] * d[2] : R(0));
     const R uu = s.u[0] * s.u[0] + s.u[1] * s.u[1] + (DIM == 3 ? s.u[2] * s.u[2] : R(0));
-    // trace of X_ab = rho u_a u_b + lam (u_a d_b + u_b d_a + delta_ab u.d)
-    s.trX3 = (s.rho * uu + s.lam * R(2 + DIM) * s.ud) * R(1.0 / 3.0);
-    s.klap = c.kappa * s.rho * lap;
+    s.lam2 = R(2) * lam;
+    s.lud[0] = lam * ud;
+    s.lud[1] = R(2) * s.lud[0];
+    // trace of X_ab over 3
+    const R trX3 = (s.rho * uu + lam * R(2 + DIM) * ud) * R(1.0 / 3.0);
+    const R klap = c.kappa * s.rho * lap;
     if (WITH_M) {
         s.M[0] = c.kappa * d[0] * d[0];
         s.M[1] = c.kappa * d[1] * d[1];
@@ -169,10 +182,41 @@ __device__ __forceinline__ EqSite<R> eq_site(const Coefs<R> &c, R rho_dev, const
         s.Myz = DIM == 3 ? c.kappa * d[1] * d[2] : R(0);
         s.Mzx = DIM == 3 ? c.kappa * d[2] * d[0] : R(0);
     }
-    // the storage shift is the same within a weight class
-    s.st_ax = R(c.wp_ax_d * p0 - c.shift[1]);
-    s.st_off = R(c.wp_off_d * p0 - c.shift[first_off<L>()]);
+    // the static part w^p_i p0 - s_i in FP64 (the storage shift is the same
+    // within a weight class), then the class terms
+    const R st_ax = R(c.wp_ax_d * p0 - c.shift[1]);
+    const R st_off = R(c.wp_off_d * p0 - c.shift[first_off<L>()]);
+    s.stc[0] = st_ax - (R(1.5) * c.w_ax * trX3 + c.wt_ax * klap);
+    s.stc[1] = st_off - (R(1.5) * c.w_off * trX3 + c.wt_off * klap);
     return s;
+}
+
+// sum_ab e_a e_b X_ab for velocity i, from eu = e.u and ed = e.d
+template <class L, class R>
+__device__ __forceinline__ R exe(const EqSite<R> &s, int i, R eu, R ed)
+{
+    return eu * (s.rho * eu + s.lam2 * ed) + s.lud[nnz<L>(i) - 1];
+}
+
+// kappa-gradient terms sum_ab w^ab_i kappa d_a rho d_b rho of velocity i
+// (equilibrium scheme)
+template <class L, class R>
+__device__ __forceinline__ R m_terms(const Coefs<R> &c, const EqSite<R> &s, int i)
+{
+    const int e0 = L::ex[i], e1 = L::ey[i], e2 = L::ez[i];
+    const bool axis = nnz<L>(i) == 1;
+    R m = sum0<R>();
+#pragma unroll
+    for (int a = 0; a < L::DIM; a++) {
+        const bool touches = ecomp<L>(i, a) != 0;
+        R wa = axis ? (touches ? c.wm_para : c.wm_perp) : (touches ? c.wm_in : c.wm_out);
+        m += wa * s.M[a];
+    }
+    // off-diagonal weights e_a e_b / 4 (constraint list after Eq. (fi))
+    if (e0 * e1 != 0) m += R(0.25 * e0 * e1) * s.Mxy;
+    if (e1 * e2 != 0) m += R(0.25 * e1 * e2) * s.Myz;
+    if (e2 * e0 != 0) m += R(0.25 * e2 * e0) * s.Mzx;
+    return m;
 }
 
 // Equilibrium of velocity i >= 1 split into the part even in e_i (second
@@ -182,33 +226,11 @@ template <class L, bool WITH_M, class R>
 __device__ __forceinline__ void eq_pair(const Coefs<R> &c, const EqSite<R> &s, int i, const R j[3],
                                         const R d[3], R &even, R &odd)
 {
-    const int e0 = L::ex[i], e1 = L::ey[i], e2 = L::ez[i];
     const bool axis = nnz<L>(i) == 1;
-    R eu = edot<L>(i, s.u);
-    R ed = edot<L>(i, d);
-    R ej = edot<L>(i, j);
-    R ee = R(nnz<L>(i));
-    // sum_ab (e_a e_b - delta_ab / 3) X_ab
-    R eXe = s.rho * eu * eu + s.lam * (R(2) * eu * ed + ee * s.ud);
-    R w = axis ? c.w_ax : c.w_off;
-    R v = (axis ? s.st_ax : s.st_off) + w * R(1.5) * (eXe - s.trX3);
-    v -= (axis ? c.wt_ax : c.wt_off) * s.klap;
-    if (WITH_M) {
-        R m = sum0<R>();
-#pragma unroll
-        for (int a = 0; a < L::DIM; a++) {
-            const bool touches = ecomp<L>(i, a) != 0;
-            R wa = axis ? (touches ? c.wm_para : c.wm_perp) : (touches ? c.wm_in : c.wm_out);
-            m += wa * s.M[a];
-        }
-        // off-diagonal weights e_a e_b / 4 (constraint list after Eq. (fi))
-        if (e0 * e1 != 0) m += R(0.25 * e0 * e1) * s.Mxy;
-        if (e1 * e2 != 0) m += R(0.25 * e1 * e2) * s.Myz;
-        if (e2 * e0 != 0) m += R(0.25 * e2 * e0) * s.Mzx;
-        v += m;
-    }
-    even = v;
-    odd = w * ej;
+    const R w = axis ? c.w_ax : c.w_off;
+    even = (R(1.5) * w) * exe<L>(s, i, edot<L>(i, s.u), edot<L>(i, d)) + s.stc[axis ? 0 : 1];
+    if (WITH_M) even += m_terms<L>(c, s, i);
+    odd = w * edot<L>(i, j);
 }
 
 // Equilibrium of Eq. (equilibrium) for i >= 1 and Eq. (feq0) for i = 0,
@@ -236,53 +258,51 @@ __device__ __forceinline__ R equilibrium(const Coefs<R> &c, R rho_dev, const R j
     return s.rho;
 }
 
-// Forcing term F_i of section "Using a forcing method" split like eq_pair:
-// even part w_i (3 (e_i.u)(e_i.g) - u.g), odd part w_i e_i.g.
-template <class L, class R>
-__device__ __forceinline__ void force_pair(const Coefs<R> &c, int i, const R u[3], const R g[3], R ug, R &even,
-                                           R &odd)
-{
-    R eu = edot<L>(i, u);
-    R eg = edot<L>(i, g);
-    R w = nnz<L>(i) == 1 ? c.w_ax : c.w_off;
-    // (3/2)(2 (e.u)(e.g) - (2/3) u.g)
-    even = w * (R(3) * eu * eg - ug);
-    odd = w * eg;
-}
-
-// BGK collision of Eq. (latbolt) with the forcing term when FORCE: out_i =
-// f_i + omega (f_i^eq - f_i) + F_i for the populations fin (deviations from
-// the shift), the equilibrium and forcing terms evaluated per pair of
-// opposite velocities.  g: body force (FORCE only).  Returns the site
-// quantities (rho, u) for the caller's observables.
+// BGK collision of Eq. (latbolt) with the forcing term of section "Using a
+// forcing method" when FORCE: out_i = f_i + omega (f_i^eq - f_i) + F_i for
+// the populations fin (deviations from the shift).  Per pair of opposite
+// velocities, with f^eq - s = even +- odd and F = fe +- fd (fe = w (3 (e.u)
+// (e.g) - u.g), fd = w e.g):
+//   E = omega even + fe,  D = omega odd + fd,
+//   out_i = (1 - omega) f_i + (E + D),  out_opp = (1 - omega) f_opp + (E - D),
+//   out_0 = (1 - omega) f_0 + omega rho_dev - 2 sum_pairs E
+// (F_0 = -sum_{i>=1} F_i and f_0^eq = rho - sum_{i>=1} f_i^eq).  omega is
+// folded into the per-class terms.  g: body force (FORCE only).  Returns the
+// site quantities (rho, u) for the caller's observables.
 template <class L, bool FORCE, class R>
 __device__ __forceinline__ EqSite<R> collide(const Coefs<R> &c, R rho_dev, const R j[3], const R d[3], R lap,
                                              const R g[3], const R fin[L::Q], R out[L::Q])
 {
     const EqSite<R> s = eq_site<L, !FORCE>(c, rho_dev, j, d, lap);
-    const R ug = FORCE ? s.u[0] * g[0] + s.u[1] * g[1] + (L::DIM == 3 ? s.u[2] * g[2] : R(0)) : R(0);
-    R sum = sum0<R>(), fsum = sum0<R>();
+    const R om = c.omega, keep = R(1) - c.omega;
+    // per-class constant part of E: omega stc - w u.g
+    R K[2] = {om * s.stc[0], om * s.stc[1]};
+    if (FORCE) {
+        const R ug = s.u[0] * g[0] + s.u[1] * g[1] + (L::DIM == 3 ? s.u[2] * g[2] : R(0));
+        K[0] -= c.w_ax * ug;
+        K[1] -= c.w_off * ug;
+    }
+    R sumE = sum0<R>();
 #pragma unroll
     for (int i = 1; i < L::Q; i++) {
         if (opp<L>(i) < i) continue;
         const int o = opp<L>(i);
-        R even, odd;
-        eq_pair<L, !FORCE>(c, s, i, j, d, even, odd);
-        sum += even;
-        R fi = fin[i], fo = fin[o];
-        out[i] = fi + c.omega * (even + odd - fi);
-        out[o] = fo + c.omega * (even - odd - fo);
+        const bool axis = nnz<L>(i) == 1;
+        const R w = axis ? c.w_ax : c.w_off;
+        const R eu = edot<L>(i, s.u);
+        R E = (R(1.5) * om * w) * exe<L>(s, i, eu, edot<L>(i, d)) + K[axis ? 0 : 1];
+        if (!FORCE) E += om * m_terms<L>(c, s, i);
+        R D = (om * w) * edot<L>(i, j);
         if (FORCE) {
-            R fe, fd;
-            force_pair<L>(c, i, s.u, g, ug, fe, fd);
-            fsum += fe;
-            out[i] += fe + fd;
-            out[o] += fe - fd;
+            const R eg = edot<L>(i, g);
+            E += (R(3) * w * eu) * eg;
+            D += w * eg;
         }
+        sumE += E;
+        out[i] = keep * fin[i] + (E + D);
+        out[o] = keep * fin[o] + (E - D);
     }
-    const R f0 = fin[0];
-    out[0] = f0 + c.omega * (rho_dev - R(2) * sum - f0);
-    if (FORCE) out[0] += R(-2) * fsum;
+    out[0] = keep * fin[0] + (om * rho_dev - R(2) * sumE);
     return s;
 }
 

@@ -120,7 +120,13 @@ __device__ __forceinline__ void step_tile(const Job<R> &J, const Coefs<R> &c)
     constexpr int HY = L::DIM == 3 ? H : 0;     // in-plane y halo
     constexpr int TXH = TX + 2 * H, TYH = TY + 2 * HY;
     constexpr int PL = TXH * TYH;               // LDS sites per density plane
-    constexpr int NR = FORCE ? 5 : 4;           // density ring depth
+    // Density ring depth: planes lc - 1 .. lc + H + 1 are live (5 for the
+    // forcing scheme, 4 for the equilibrium scheme).  RP2 rounds the rings
+    // up to powers of two, so that a ring slot is a mask, not a division:
+    // faster for FP64 storage and D2Q9; for D3Q19 FP32 the extra uniform
+    // address terms push the kernel to 256 VGPRs and it runs 2.5 % slower.
+    constexpr bool RP2 = sizeof(S) == 8 || L::DIM == 2;
+    constexpr int NR = FORCE ? (RP2 ? 8 : 5) : 4;
     constexpr int GY = L::DIM == 3 ? 1 : 0;     // gradient ring in-plane y halo
     constexpr int TXG = TX + 2, TYG = TY + 2 * GY;
     constexpr int GPL = TXG * TYG;
@@ -139,7 +145,8 @@ __device__ __forceinline__ void step_tile(const Job<R> &J, const Coefs<R> &c)
     // the fly from the stored gradient.
     constexpr bool TT = FORCE && sizeof(R) == 4;
     constexpr int NG = TT ? (L::DIM == 3 ? 9 : 4) : 3;
-    __shared__ R grad_s[FORCE ? 3 * NG * GPL : 1];
+    constexpr int NGR = RP2 ? 4 : 3;  // gradient ring depth (3 planes live)
+    __shared__ R grad_s[FORCE ? NGR * NG * GPL : 1];
 
     const S *src = static_cast<const S *>(J.src);
     S *dst = static_cast<S *>(J.dst);
@@ -232,19 +239,20 @@ __device__ __forceinline__ void step_tile(const Job<R> &J, const Coefs<R> &c)
     };
 
     auto rho_at = [&](int lp, int lx, int ly) -> R & {
-        return rho_s[(lp % NR) * PL + ly * TXH + lx];
+        return rho_s[(unsigned(lp) % NR) * PL + ly * TXH + lx];
     };
 
     // local plane lp is global plane p0 - H + lp: issue the loads of its own
     // site (into f) or of its halo sites (into h); store their densities
-    auto load_own = [&](int lp, R(&f)[Q]) {
+    // (pg: the global plane index of lp, wrapped)
+    auto load_own = [&](int pg, R(&f)[Q]) {
         int P[3];
-        plane_offsets(wrapg(p0 - H + lp, np), P);
+        plane_offsets(pg, P);
         pull(X, Y, P, f);
     };
-    auto load_halo = [&](int lp, R(&h)[NHT][Q]) {
+    auto load_halo = [&](int pg, R(&h)[NHT][Q]) {
         int P[3];
-        plane_offsets(wrapg(p0 - H + lp, np), P);
+        plane_offsets(pg, P);
         // With HA = 2 threads without a halo site load a valid dummy site
         // (lx = ly = 0) and ignore it: without a branch the compiler can
         // count these loads and leave them in flight at the next wait.
@@ -253,7 +261,7 @@ __device__ __forceinline__ void step_tile(const Job<R> &J, const Coefs<R> &c)
             if (HA == 2 || hv[s]) pull(hX[s], hY[s], P, h[s]);
     };
     auto store_rho = [&](int lp, const R(&f)[Q], const R(&h)[NHT][Q]) {
-        R *ring = rho_s + (lp % NR) * PL;
+        R *ring = rho_s + (unsigned(lp) % NR) * PL;
         ring[(ty + HY) * TXH + tx + H] = dens(f);
 #pragma unroll
         for (int s = 0; s < NHT; s++)
@@ -262,7 +270,7 @@ __device__ __forceinline__ void step_tile(const Job<R> &J, const Coefs<R> &c)
 
     // gradient of rho on the tile + 1 ring of local plane lp (forcing only)
     auto grad_at = [&](int lp, int comp, int lx, int ly) -> R & {
-        return grad_s[((lp % 3) * NG + comp) * GPL + ly * TXG + lx];
+        return grad_s[((unsigned(lp) % NGR) * NG + comp) * GPL + ly * TXG + lx];
     };
     // component index of T_ab in the ring (TT only); 2D T_yy is -T_xx
     auto t_comp = [](int a, int b) constexpr -> int {
@@ -315,24 +323,33 @@ __device__ __forceinline__ void step_tile(const Job<R> &J, const Coefs<R> &c)
 
     // prologue: densities of planes p0-H .. p0+H (own populations of
     // p0 .. p0+H kept in fr[0..H]), gradients of p0-1, p0
+    // (uniform across the workgroup: readfirstlane keeps the plane
+    // arithmetic in scalar registers instead of the vector ALU)
+    auto gplane = [&](int lp) { return __builtin_amdgcn_readfirstlane(wrapg(p0 - H + lp, np)); };
     for (int lp = 0; lp < H; lp++) {
-        load_own(lp, fr[H + 1]);
-        load_halo(lp, hr[0]);
+        load_own(gplane(lp), fr[H + 1]);
+        load_halo(gplane(lp), hr[0]);
         store_rho(lp, fr[H + 1], hr[0]);
     }
 #pragma unroll
     for (int s = 0; s <= H; s++) {
-        load_own(H + s, fr[s]);
-        load_halo(H + s, hr[0]);
+        load_own(gplane(H + s), fr[s]);
+        load_halo(gplane(H + s), hr[0]);
         store_rho(H + s, fr[s], hr[0]);
     }
     // with HA = 2 the halo of plane 2H + 1 (the first front) is loaded here
-    if (HA == 2 && npl > 1) load_halo(2 * H + 1, hr[0]);
+    if (HA == 2 && npl > 1) load_halo(gplane(2 * H + 1), hr[0]);
     __syncthreads();
     if (FORCE) {
         fill_grad(1);
         fill_grad(2);
     }
+
+    // Global indices (wrapped) of the plane collided, of the own-site load
+    // front and of the halo load front, advanced by one plane per iteration
+    // (uniform values: a compare and select, not a division).
+    int pg_c = gplane(H), pg_f = gplane(2 * H + 1), pg_h = gplane(2 * H + HA);
+    auto advance = [&](int &pg) { pg = pg + 1 == np ? 0 : pg + 1; };
 
     // One plane.  The register ring is indexed at compile time: plane H + k
     // lives in fr[k mod (H + 2)], so the loop below is unrolled H + 2 times
@@ -347,8 +364,8 @@ __device__ __forceinline__ void step_tile(const Job<R> &J, const Coefs<R> &c)
         const int lc = H + k;  // local index of the plane collided now
         const bool more = decltype(always_more)::value || k + 1 < npl;
         const bool more_h = decltype(always_more)::value || k + HA < npl;
-        if (more) load_own(lc + H + 1, fr[CN]);  // consumed after the collision
-        if (more_h) load_halo(lc + H + HA, hr[HN]);
+        if (more) load_own(pg_f, fr[CN]);  // plane lc + H + 1, consumed after the collision
+        if (more_h) load_halo(pg_h, hr[HN]);  // plane lc + H + HA
         __syncthreads();  // densities up to plane lc + H are in LDS
         if (FORCE) {
             fill_grad(lc + 1);
@@ -424,7 +441,7 @@ __device__ __forceinline__ void step_tile(const Job<R> &J, const Coefs<R> &c)
             g[1] *= kg;
             g[2] *= kg;
         }
-        const int p = wrapg(p0 + k, np);
+        const int p = pg_c;
         const unsigned site = unsigned(p * psz + Y[1] + X[1]);
         // collided populations (stored below)
         R out[Q];
@@ -449,6 +466,9 @@ __device__ __forceinline__ void step_tile(const Job<R> &J, const Coefs<R> &c)
 #pragma unroll
             for (int i = 0; i < Q; i++) buf_store(rd, site * ES, unsigned(i * stride) * ES, S(out[i]));
         }
+        advance(pg_c);
+        advance(pg_f);
+        advance(pg_h);
     };
 
     // Full groups of H + 2 planes, every one of which prefetches: the loads
