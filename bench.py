@@ -18,6 +18,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -53,11 +54,24 @@ def make_workload(wl):
     return p, rho0
 
 
-def kernel_hash():
+def _code_only(text):
+    """Source text without comments and blank lines: a comment edit does not
+    change the kernel the counters were taken on."""
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", "", text)
+    return "\n".join(line.rstrip() for line in text.splitlines() if line.strip())
+
+
+def kernel_hash(sources=None):
+    """Hash of the step kernel's code (comments and blank lines excluded)."""
     h = hashlib.sha256()
     for rel in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, rel), "rb") as fh:
-            h.update(fh.read())
+        if sources is None:
+            with open(os.path.join(ROOT, rel)) as fh:
+                text = fh.read()
+        else:
+            text = sources[rel]
+        h.update(_code_only(text).encode())
     return h.hexdigest()[:16]
 
 

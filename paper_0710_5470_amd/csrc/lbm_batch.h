@@ -120,9 +120,9 @@ __global__ __launch_bounds__(RED_THREADS) void batch_check_kernel(
         } else if (v[1] <= tol) {
             s.status = BST_CONVERGED;
         } else {
-            const bool judged = s.steps > grace;
-            s.rises = (judged && s.best > 0.0 && v[1] > RISE_FACTOR * s.best) ? s.rises + 1 : 0;
-            if (judged && (s.best == 0.0 || v[1] < s.best)) s.best = v[1];
+            const bool past_grace = s.steps > grace;
+            s.rises = (past_grace && s.best > 0.0 && v[1] > RISE_FACTOR * s.best) ? s.rises + 1 : 0;
+            if (past_grace && (s.best == 0.0 || v[1] < s.best)) s.best = v[1];
             if (patience > 0 && s.rises >= patience) s.status = BST_DIVERGED;
             else if (s.steps >= max_steps) s.status = BST_MAXSTEPS;
         }

@@ -454,8 +454,9 @@ __device__ __forceinline__ void step_tile(const Job<R> &J, const Coefs<R> &c)
             J.obs_vel[2 * J.obs_stride + site] = double(L::DIM == 3 ? es.u[2] + h * g[2] : R(0));
         }
         // Densities of the next plane: its ring slot (plane lc+H+1) is read by
-        // no thread in this iteration (ring depths 4 and 5), so no barrier is
-        // needed before this store; the next iteration's first barrier
+        // no thread in this iteration (the ring holds at least the H + 3
+        // planes lc - 1 .. lc + H + 1), so no barrier is needed before this
+        // store; the next iteration's first barrier
         // publishes it.  The next gradient fill overwrites a plane read above
         // only after that barrier.
         if (more) store_rho(lc + H + 1, fr[CN], hr[HB]);

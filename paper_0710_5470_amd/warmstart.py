@@ -6,7 +6,7 @@ initial density to a near-steady (rho, u_x, u_y) field.  The prediction is
 averaged over the square's eight symmetries (the centred drop's steady state
 has them) and given the cold start's mass and zero momentum.  The batched
 lattice Boltzmann runner then starts from the equilibrium of that field,
-judges convergence by its own residual and falls back to a cold start for
+decides convergence by its own residual and falls back to a cold start for
 any problem whose residual rises tenfold above its best.
 
 Every arithmetic step of the network runs in this library's HIP kernels
