@@ -83,6 +83,18 @@ __device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, unsigned vof
 #ifndef LBM_STEP_WAVES_PER_EU
 #define LBM_STEP_WAVES_PER_EU 1
 #endif
+// The same for the batched (persistent) kernel; 0 = per instance: three
+// waves per SIMD for the D2Q9 FP64 equilibrium kernel (172 -> 168 VGPRs,
+// 4 dwords spilled; 2 % off the batched time-to-steady of 512 drops), the
+// compiler's choice elsewhere (the larger kernels would spill heavily).
+#ifndef LBM_BATCH_WAVES_PER_EU
+#define LBM_BATCH_WAVES_PER_EU 0
+#endif
+template <class L, int SCHEME, class S> constexpr int batch_waves_per_eu()
+{
+    if (LBM_BATCH_WAVES_PER_EU > 0) return LBM_BATCH_WAVES_PER_EU;
+    return (L::DIM == 2 && SCHEME == SCHEME_EQ && sizeof(S) == 8) ? 3 : 1;
+}
 
 // Planes ahead of the density front at which the forcing scheme loads its
 // halo populations: 1, 2, or 0 = 2 for FP64 storage and 1 for FP32.
@@ -560,7 +572,7 @@ template <class R> struct BatchArgs {
 // one tile x chunk of one problem (binary search over item0).  Items of
 // inactive problems are skipped, so converged problems keep their state.
 template <class L, int SCHEME, class S, class R, int TX, int TY>
-__global__ __launch_bounds__(TX *TY) __attribute__((amdgpu_waves_per_eu(LBM_STEP_WAVES_PER_EU)))
+__global__ __launch_bounds__(TX *TY) __attribute__((amdgpu_waves_per_eu(batch_waves_per_eu<L, SCHEME, S>())))
 void batch_step_kernel(BatchArgs<R> B)
 {
     for (int w = blockIdx.x; w < B.nitems; w += gridDim.x) {
