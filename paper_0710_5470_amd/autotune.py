@@ -94,10 +94,15 @@ def _batch_key(plist):
 
 
 def batch_candidates(plist):
+    """(tile, planes per work item) pairs: powers of two, and the plane counts
+    that cut the longest marching axis into 1..8 equal chunks (so that the
+    number of work items can match the workgroups the chip holds at once,
+    e.g. 3 chunks of 43 planes for 128^2 problems)."""
     p = plist[0]
     np_max = max(q.nz if q.lattice == lbm.D3Q19 else q.ny for q in plist)
-    planes = sorted(set(min(c, np_max) for c in (8, 16, 32, 64)))
-    return [(t, c) for t in range(lbm.lbm_tile_count(p.lattice)) for c in planes]
+    planes = set(min(c, np_max) for c in (8, 16, 32, 64))
+    planes |= set(-(-np_max // k) for k in range(1, 9) if -(-np_max // k) >= 8)
+    return [(t, c) for t in range(lbm.lbm_tile_count(p.lattice)) for c in sorted(planes)]
 
 
 def autotune_batch(plist, rho0, steps=8, use_cache=True, verbose=False):
