@@ -651,36 +651,49 @@ int lbm_destroy(lbm_ctx *c)
 int lbm_coexistence(double a, double b, double T, double *rho_gas, double *rho_liq)
 {
     if (!rho_gas || !rho_liq || !(a > 0) || !(b > 0) || !(T > 0)) return LBM_E_INVAL;
-    double Tc = 8.0 * a / (27.0 * b), rc = 1.0 / (3.0 * b);
+    const double Tc = 8.0 * a / (27.0 * b), rc = 1.0 / (3.0 * b), rmax = 1.0 / b;
     if (!(T < Tc)) return LBM_E_INVAL;
-    // start from the spinodals (dp/drho = 0) pushed outwards
+    // Spinodals sg < rc < sl (dp/drho = 0), by bisection on the sign of dp/drho.
     auto spin = [&](double lo, double hi) {
+        const bool up = vdw_dp(a, b, T, lo) > 0;
         for (int k = 0; k < 200; k++) {
-            double m = 0.5 * (lo + hi);
-            if ((vdw_dp(a, b, T, lo) > 0) == (vdw_dp(a, b, T, m) > 0)) lo = m; else hi = m;
+            const double m = 0.5 * (lo + hi);
+            if ((vdw_dp(a, b, T, m) > 0) == up) lo = m; else hi = m;
         }
         return 0.5 * (lo + hi);
     };
-    double sg = spin(1e-12, rc), sl = spin(rc, (1.0 - 1e-12) / b);
-    double g = 0.5 * sg, l = std::min(sl + 0.5 * (1.0 / b - sl), 0.5 * (sl + 1.0 / b));
-    for (int it = 0; it < 200; it++) {
-        double f1 = vdw_p(a, b, T, g) - vdw_p(a, b, T, l);
-        double f2 = vdw_mu(a, b, T, g) - vdw_mu(a, b, T, l);
-        // d mu / d rho = (dp/drho) / rho
-        double j11 = vdw_dp(a, b, T, g), j12 = -vdw_dp(a, b, T, l);
-        double j21 = j11 / g, j22 = j12 / l;
-        double det = j11 * j22 - j12 * j21;
-        if (det == 0.0 || !std::isfinite(det)) return LBM_E_INVAL;
-        double dg = (f1 * j22 - f2 * j12) / det, dl = (j11 * f2 - j21 * f1) / det;
-        // damped step that keeps 0 < g < sg and sl < l < 1/b
-        double s = 1.0;
-        while ((g - s * dg <= 0 || g - s * dg >= sg || l - s * dl <= sl || b * (l - s * dl) >= 1) &&
-               s > 1e-12)
-            s *= 0.5;
-        g -= s * dg;
-        l -= s * dl;
-        if (std::fabs(s * dg) < 1e-15 * g && std::fabs(s * dl) < 1e-15 * l) break;
+    const double sg = spin(0.0, rc), sl = spin(rc, rmax);
+    if (!(0.0 < sg && sg < rc && rc < sl && sl < rmax)) return LBM_E_INVAL;
+    // mu increases with rho on both stable branches (d mu / d rho = (dp/drho)
+    // / rho > 0), so the density with a given mu is found by bisection on
+    // each: the gas branch (0, sg) and the liquid branch (sl, 1/b).
+    auto on_branch = [&](double mu, double lo, double hi) {
+        for (int k = 0; k < 200; k++) {
+            const double m = 0.5 * (lo + hi);
+            if (vdw_mu(a, b, T, m) < mu) lo = m; else hi = m;
+        }
+        return 0.5 * (lo + hi);
+    };
+    // Maxwell construction: the common mu of the two phases makes their
+    // pressures equal.  Between mu(sl) and mu(sg), p(liquid) - p(gas) rises
+    // from negative to positive; bisect on mu.
+    double mlo = vdw_mu(a, b, T, sl), mhi = vdw_mu(a, b, T, sg);
+    if (!(mlo < mhi)) return LBM_E_INVAL;
+    double g = 0.0, l = 0.0;
+    for (int k = 0; k < 200; k++) {
+        const double m = 0.5 * (mlo + mhi);
+        g = on_branch(m, 0.0, sg);
+        l = on_branch(m, sl, rmax);
+        if (vdw_p(a, b, T, l) - vdw_p(a, b, T, g) < 0) mlo = m; else mhi = m;
+        if (!(mlo < 0.5 * (mlo + mhi) && 0.5 * (mlo + mhi) < mhi)) break;  // interval exhausted
     }
+    // the result must be a coexistence point, not just the end of the search
+    const double pg = vdw_p(a, b, T, g), pl = vdw_p(a, b, T, l);
+    const double ug = vdw_mu(a, b, T, g), ul = vdw_mu(a, b, T, l);
+    const double pscale = std::fabs(vdw_p(a, b, T, sg)) + std::fabs(vdw_p(a, b, T, sl)) + T * rc;
+    if (!(0.0 < g && g < sg && sl < l && l < rmax) || !(std::fabs(pl - pg) <= 1e-9 * pscale) ||
+        !(std::fabs(ul - ug) <= 1e-9 * (std::fabs(ug) + T)))
+        return LBM_E_INVAL;
     *rho_gas = g;
     *rho_liq = l;
     return LBM_OK;

@@ -60,8 +60,9 @@ def test_tile_shapes():
 
 @pytest.mark.parametrize("T", [0.45, 0.5, 0.53, 0.56, 0.57])
 def test_host_coexistence_matches_oracle(T):
-    """The library's Newton solver against the oracle's independent nested
-    bracketing (both solve the Maxwell construction for Eq. (p0))."""
+    """The library's solver (bisection on the chemical potential) against
+    the oracle's independent one (bracketing on the pressure); both solve the
+    Maxwell construction for Eq. (p0)."""
     from paper_0710_5470_amd import lbm
     from oracle import thermo
     a, b = 9 / 49, 2 / 21
@@ -70,3 +71,17 @@ def test_host_coexistence_matches_oracle(T):
     assert g == pytest.approx(g2, rel=1e-10) and l == pytest.approx(l2, rel=1e-10)
     with pytest.raises(lbm.LBMError):
         lbm.lbm_coexistence(a, b, 4 / 7 + 1e-9)
+
+
+def test_host_coexistence_on_a_dense_temperature_grid():
+    """Every temperature of a dense grid, and T = 0.549410056920318, where an
+    earlier damped Newton solver stalled and returned densities 0.62 / 9.51
+    (no coexistence point) with a success status."""
+    import numpy as np
+    from paper_0710_5470_amd import lbm
+    from oracle import thermo
+    a, b = 9 / 49, 2 / 21
+    for T in list(np.linspace(0.40, 0.57, 341)) + [0.549410056920318]:
+        g, l = lbm.lbm_coexistence(a, b, float(T))
+        g2, l2, _ = thermo.coexistence(a, b, float(T))
+        assert g == pytest.approx(g2, rel=1e-9) and l == pytest.approx(l2, rel=1e-9), T
