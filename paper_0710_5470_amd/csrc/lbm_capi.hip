@@ -654,10 +654,13 @@ int lbm_coexistence(double a, double b, double T, double *rho_gas, double *rho_l
     const double Tc = 8.0 * a / (27.0 * b), rc = 1.0 / (3.0 * b), rmax = 1.0 / b;
     if (!(T < Tc)) return LBM_E_INVAL;
     // Spinodals sg < rc < sl (dp/drho = 0), by bisection on the sign of dp/drho.
+    // (Each bisection stops once the midpoint is no longer strictly inside
+    // the interval: the two ends are adjacent doubles.)
     auto spin = [&](double lo, double hi) {
         const bool up = vdw_dp(a, b, T, lo) > 0;
-        for (int k = 0; k < 200; k++) {
+        for (int k = 0; k < 2100; k++) {
             const double m = 0.5 * (lo + hi);
+            if (!(lo < m && m < hi)) break;
             if ((vdw_dp(a, b, T, m) > 0) == up) lo = m; else hi = m;
         }
         return 0.5 * (lo + hi);
@@ -668,8 +671,9 @@ int lbm_coexistence(double a, double b, double T, double *rho_gas, double *rho_l
     // / rho > 0), so the density with a given mu is found by bisection on
     // each: the gas branch (0, sg) and the liquid branch (sl, 1/b).
     auto on_branch = [&](double mu, double lo, double hi) {
-        for (int k = 0; k < 200; k++) {
+        for (int k = 0; k < 2100; k++) {
             const double m = 0.5 * (lo + hi);
+            if (!(lo < m && m < hi)) break;
             if (vdw_mu(a, b, T, m) < mu) lo = m; else hi = m;
         }
         return 0.5 * (lo + hi);
@@ -680,12 +684,12 @@ int lbm_coexistence(double a, double b, double T, double *rho_gas, double *rho_l
     double mlo = vdw_mu(a, b, T, sl), mhi = vdw_mu(a, b, T, sg);
     if (!(mlo < mhi)) return LBM_E_INVAL;
     double g = 0.0, l = 0.0;
-    for (int k = 0; k < 200; k++) {
+    for (int k = 0; k < 2100; k++) {
         const double m = 0.5 * (mlo + mhi);
         g = on_branch(m, 0.0, sg);
         l = on_branch(m, sl, rmax);
+        if (!(mlo < m && m < mhi)) break;
         if (vdw_p(a, b, T, l) - vdw_p(a, b, T, g) < 0) mlo = m; else mhi = m;
-        if (!(mlo < 0.5 * (mlo + mhi) && 0.5 * (mlo + mhi) < mhi)) break;  // interval exhausted
     }
     // the result must be a coexistence point, not just the end of the search
     const double pg = vdw_p(a, b, T, g), pl = vdw_p(a, b, T, l);

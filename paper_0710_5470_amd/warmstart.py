@@ -201,11 +201,13 @@ def warm_start(net, specs, side, tol=1e-10, check_every=100, max_steps=60000, pa
     """Predict, project (lbm_warm_project), run with the rising-residual
     check; problems that diverge are rerun from the cold start.  Returns the
     steady_states dict with per-problem total steps, final statuses, the
-    fallback mask and wall seconds including inference."""
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
+    fallback mask and wall seconds including inference (features, network,
+    projection).  The problems themselves (parameters and cold initial
+    densities) are built before the clock starts, as in steady_states."""
     n = len(specs)
     _, rho0 = problems(specs, side)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
     pred = net.predict(features(specs, side, rho0))
     rho_p = torch.empty(n * side * side, dtype=torch.float64, device=net.dev)
     u_p = torch.empty(3, n * side * side, dtype=torch.float64, device=net.dev)
