@@ -199,7 +199,8 @@ def steady_states(specs, side, tol=1e-10, check_every=100, max_steps=60000, rho_
 def warm_start(net, specs, side, tol=1e-10, check_every=100, max_steps=60000, patience=3,
                grace=500, symmetrize=True, with_velocity=False, settle_tol=None):
     """Predict, project (lbm_warm_project), run with the rising-residual
-    check; problems that diverge are rerun from the cold start.  Returns the
+    check; problems that diverge or go non-finite are rerun from the cold
+    start.  Returns the
     steady_states dict with per-problem total steps, final statuses, the
     fallback mask and wall seconds including inference (features, network,
     projection).  The problems themselves (parameters and cold initial
@@ -217,7 +218,8 @@ def warm_start(net, specs, side, tol=1e-10, check_every=100, max_steps=60000, pa
     t_inf = time.perf_counter() - t0
     run = steady_states(specs, side, tol, check_every, max_steps, rho_init=rho_p, u_init=u_p,
                         patience=patience, grace=grace, settle_tol=settle_tol)
-    fallback = run["status"] == lbm.BATCH_DIVERGED
+    # rising residual, or a state that went non-finite: rerun from the cold start
+    fallback = (run["status"] == lbm.BATCH_DIVERGED) | (run["status"] == lbm.BATCH_NONFINITE)
     total = run["steps"].copy()
     status = run["status"].copy()
     secs_fb = 0.0
