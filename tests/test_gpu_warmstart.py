@@ -32,3 +32,32 @@ def test_trained_warm_start_beats_cold_start():
     # thin-interface drops may settle with the interface pinned at another
     # lattice position; they must stay a small minority
     assert len(warm["other_steady_state"]) <= 6
+
+
+class _WildNet:
+    """Stands in for the network: predicts a shear flow u_x = +-2 (far
+    beyond the lattice sound speed) that the projection keeps (zero mean
+    momentum), so every warm run becomes non-finite or diverges."""
+    dev = torch.device("cuda") if torch.cuda.is_available() else None
+
+    def predict(self, x):
+        from paper_0710_5470_amd import warmstart
+        n, side = x.shape[0], x.shape[1]
+        y = torch.zeros(n, side, side, warmstart.CP_OUT, dtype=torch.float32, device="cuda")
+        rows = torch.arange(side, device="cuda").view(1, side, 1)
+        y[..., 1] = torch.where(rows < side // 2, 2000.0, -2000.0)
+        return y
+
+
+def test_failed_warm_start_falls_back_to_cold():
+    from paper_0710_5470_amd import inputs, lbm, warmstart
+    print("[gpu-case] warm start fallback, 8 drops of 64^2", flush=True)
+    specs = inputs.stable_batch_specs(8, 6, side_lo=64, side_hi=64)
+    w = warmstart.warm_start(_WildNet(), specs, 64, tol=1e-10, symmetrize=False,
+                             with_velocity=True)
+    cold = warmstart.steady_states(specs, 64, 1e-10)
+    print("[gpu-case] fallbacks %d, statuses %s" % (int(w["fallback"].sum()), w["status"].tolist()),
+          flush=True)
+    assert w["fallback"].all()
+    assert (w["status"] == lbm.BATCH_CONVERGED).all()
+    assert (w["steps"] > cold["steps"]).all()
