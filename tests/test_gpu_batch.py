@@ -127,3 +127,35 @@ def test_reactivated_batch_continues_to_a_tighter_residual():
         one.close()
         seg = rho_two[sum(p.nx * p.ny for p in plist[:k]):][:plist[k].nx * plist[k].ny]
         assert torch.equal(seg, r_one)
+
+
+def test_full_size_batch_matches_oracle_on_sampled_problems():
+    """The batched time-to-steady workload at full size (512 drops of 128^2,
+    FP64, tau = 1) in the launch the batch autotuner picks for it, 6 steps;
+    four sampled problems (first, last, and two inside, among them the one
+    with T = 0.549410) against the oracle: 1e-12 relative on rho and 1e-12
+    absolute on u, as for the single-lattice FP64 parity."""
+    import oracle
+    from paper_0710_5470_amd import autotune, inputs, lbm
+    from paper_0710_5470_amd import warmstart as ws
+    specs = inputs.stable_batch_specs(512, 6, side_lo=128, side_hi=128)
+    plist, rho0 = ws.problems(specs, 128)
+    launch = autotune.autotune_batch(plist, rho0, use_cache=False)
+    _say("full-size batch, 512 x 128^2, launch", launch)
+    bt = lbm.Batch(plist, rho0)
+    bt.set_launch(*launch)
+    bt.step(6)
+    r, v = bt.moments()
+    rs, vs = bt.split(r), bt.split(v)
+    r0 = rho0.cpu().numpy().reshape(512, 128, 128)
+    for k in (0, 137, 444, 511):
+        p = plist[k]
+        op = oracle.params(q=9, scheme=0, shape=(128, 128), T=p.T, kappa=p.kappa, tau=1.0)
+        ro, vo = oracle.observe(op, oracle.run(op, oracle.init(op, r0[k]), 6))
+        rg = rs[k].cpu().numpy()
+        vg = vs[k].cpu().numpy()
+        er = float(np.max(np.abs(rg - ro) / ro))
+        ev = float(np.max(np.abs(vg[:2] - vo[:2])))
+        _say("problem %d: rel err rho %.2e, abs err u %.2e" % (k, er, ev))
+        assert er < 1e-12 and ev < 1e-12
+    bt.close()
