@@ -102,8 +102,8 @@ template <class L, int SCHEME, class S> constexpr int batch_waves_per_eu()
 // with 2, the halo loads (mostly L2 hits) for the plane after next go out
 // behind them, so the wait for the own loads leaves them in flight.  This
 // costs 19 registers and a load from every thread, also those without a
-// halo site: it pays for FP64 populations (D3Q19 256^3: 1.626 against
-// 1.688 ms per step) and not for FP32 (0.747 against 0.684 ms).
+// halo site: it paid for FP64 populations when introduced (D3Q19 256^3:
+// 1.626 against 1.688 ms per step) and not for FP32 (0.747 against 0.684 ms).
 #ifndef LBM_HALO_AHEAD
 #define LBM_HALO_AHEAD 0
 #endif
@@ -335,8 +335,9 @@ __device__ __forceinline__ void step_tile(const Job<R> &J, const Coefs<R> &c)
 
     // prologue: densities of planes p0-H .. p0+H (own populations of
     // p0 .. p0+H kept in fr[0..H]), gradients of p0-1, p0
-    // (uniform across the workgroup: readfirstlane keeps the plane
-    // arithmetic in scalar registers instead of the vector ALU)
+    // (uniform across the workgroup, and marked so for the compiler; where
+    // scalar registers run short, as in the D3Q19 FP32 forcing kernel, it
+    // still keeps these values in vector registers)
     auto gplane = [&](int lp) { return __builtin_amdgcn_readfirstlane(wrapg(p0 - H + lp, np)); };
     for (int lp = 0; lp < H; lp++) {
         load_own(gplane(lp), fr[H + 1]);
