@@ -91,7 +91,8 @@ def measured_traffic(workload):
 def cpu_baseline(wl):
     """Time the FP64 CPU oracle on a bounded sample of the same workload: a
     256 x 256 x 48 periodic slab (D3Q19) or a 1024 x 1024 box (D2Q9) with
-    the same parameters, 6 steps, all host threads OpenMP allows."""
+    the same parameters, about 10 s of oracle steps on all host threads
+    OpenMP allows (36 steps of the slab, 150 of the box, on 16 cores)."""
     import numpy as np
     import oracle
     from paper_0710_5470_amd import inputs
@@ -104,7 +105,7 @@ def cpu_baseline(wl):
         rho = rho + inputs.uniform_noise(sample, noise, 3)
     p = oracle.params(q=q, scheme=scheme, shape=sample, T=T, kappa=kappa, tau=tau)
     f = oracle.init(p, rho)
-    steps = 6
+    steps = 36 if q == 19 else 150
     t0 = time.perf_counter()
     f = oracle.run(p, f, steps)
     dt = time.perf_counter() - t0
