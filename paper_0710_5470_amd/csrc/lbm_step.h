@@ -97,13 +97,15 @@ template <class L, int SCHEME, class S> constexpr int batch_waves_per_eu()
 }
 
 // Planes ahead of the density front at which the forcing scheme loads its
-// halo populations: 1, 2, or 0 = 2 for FP64 storage and 1 for FP32.
+// halo populations: 1, 2, or 0 = 2 for FP64 arithmetic and 1 for FP32.
 // Own-site loads (from HBM) are always one plane ahead and issued first;
 // with 2, the halo loads (mostly L2 hits) for the plane after next go out
 // behind them, so the wait for the own loads leaves them in flight.  This
 // costs 19 registers and a load from every thread, also those without a
-// halo site: it paid for FP64 populations when introduced (D3Q19 256^3:
-// 1.626 against 1.688 ms per step) and not for FP32 (0.747 against 0.684 ms).
+// halo site: it pays where the kernel computes in FP64, which already runs
+// one wave per SIMD (D3Q19 256^3: 1.626 against 1.688 ms per step for FP64
+// storage, 1.08 against 1.18 ms for FP32 storage with FP64 arithmetic), and
+// not for FP32 arithmetic (0.747 against 0.684 ms).
 #ifndef LBM_HALO_AHEAD
 #define LBM_HALO_AHEAD 0
 #endif
@@ -223,7 +225,7 @@ __device__ __forceinline__ void step_tile(const Job<R> &J, const Coefs<R> &c)
     // memory latency of plane p + H + 1 overlaps the arithmetic of plane p).
     // hr holds the in-flight halo populations, HA planes deep.
     constexpr int HA =
-        FORCE && (LBM_HALO_AHEAD == 2 || (LBM_HALO_AHEAD == 0 && sizeof(S) == 8)) ? 2 : 1;
+        FORCE && (LBM_HALO_AHEAD == 2 || (LBM_HALO_AHEAD == 0 && sizeof(R) == 8)) ? 2 : 1;
     R fr[H + 2][Q];
     R hr[HA][NHT][Q];
 
