@@ -46,7 +46,10 @@ def coexistence(a, b, T):
 
     For a trial pressure P between the spinodal pressures, take the outermost
     roots of p0(rho) = P on the gas and liquid branches; adjust P until the
-    chemical potentials match.  Returns (rho_gas, rho_liquid, P)."""
+    chemical potentials match.  Returns (rho_gas, rho_liquid, P).  The
+    pressure bracket starts at 1e-14, so temperatures whose coexistence
+    pressure is below that (T <= 0.05 for a = 9/49, b = 2/21) are not
+    handled."""
     s_lo, s_hi = _spinodals(a, b, T)
     p_min, p_max = p0(a, b, T, s_hi), p0(a, b, T, s_lo)
     p_lo = max(p_min, 1e-14)
