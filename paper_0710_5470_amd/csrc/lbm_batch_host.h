@@ -357,7 +357,7 @@ int lbm_batch_init(lbm_batch **out, int nprob, const lbm_params *pp, void *dev_w
         double rs = std::isnan(pp[k].rho_shift) ? mean : pp[k].rho_shift;
         cd[k] = make_coefs(&pp[k]);
         make_shift(&pp[k], cd[k], rs);
-        cf[k] = to_float(cd[k]);
+        cf[k] = to_float(cd[k], pp[k].lattice);
     }
     const bool f32math = bt->base.storage != LBM_STORE_F64 && bt->base.compute == LBM_COMPUTE_NATIVE;
     hipError_t e = f32math ? hipMemcpyAsync(bptr<char>(bt, bt->o_coef), cf.data(), nprob * sizeof(Coefs<float>),

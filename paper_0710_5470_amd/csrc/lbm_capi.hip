@@ -151,6 +151,8 @@ Coefs<double> make_coefs(const lbm_params *p)
     c.T = p->T;
     c.kappa = p->kappa;
     c.omega = 1.0 / p->tau;
+    c.ow_ax = c.omega * c.w_ax;
+    c.ow_off = c.omega * c.w_off;
     c.nu = (p->tau - 0.5) / 3.0;
     c.lambda_on = p->galilean_lambda ? 1 : 0;
     c.wp_ax_d = c.wp_ax;
@@ -182,18 +184,41 @@ void make_shift(const lbm_params *p, Coefs<double> &c, double rho0)
     c.shift_sum = sum + c.shift[0];
 }
 
-Coefs<float> to_float(const Coefs<double> &d)
+// FP32 weights (a, o) of the axis and off-axis classes with 2 a + m o = t
+// holding exactly (m: off-axis velocities with a nonzero component along a
+// given axis, 4 in D2Q9 and 8 in D3Q19).  One of the two is rounded, the
+// other solved for; the first choice whose identity holds exactly is kept
+// (both are exact in FP64, which holds the products of FP32 values
+// exactly).  Rounding both independently would break the first-moment
+// identity sum_i w_i e_ia e_ib = delta_ab by ~1e-8: the collision would then
+// create momentum omega (2 a + m o - 1) j every step, a bias that moves the
+// FP32 state away from the conserved dynamics.
+void exact_pair(double a, double o, float t, int m, float &fa, float &fo)
+{
+    fa = float(a);
+    fo = float((double(t) - 2.0 * double(fa)) / m);
+    if (2.0 * double(fa) + m * double(fo) == double(t)) return;
+    fo = float(o);
+    fa = float((double(t) - m * double(fo)) / 2.0);
+    if (2.0 * double(fa) + m * double(fo) == double(t)) return;
+    fa = float(a);  // no exact pair: plain rounding
+    fo = float(o);
+}
+
+Coefs<float> to_float(const Coefs<double> &d, int lattice)
 {
     Coefs<float> f{};
+    const int m = lattice == LBM_D3Q19 ? 8 : 4;
     f.A = float(d.A); f.B = float(d.B); f.C = float(d.C); f.D = float(d.D);
     f.Ef = float(d.Ef); f.Ff = float(d.Ff);
-    f.w_ax = float(d.w_ax); f.w_off = float(d.w_off);
+    f.omega = float(d.omega);
+    exact_pair(d.w_ax, d.w_off, 1.0f, m, f.w_ax, f.w_off);
+    exact_pair(d.ow_ax, d.ow_off, f.omega, m, f.ow_ax, f.ow_off);
     f.wp_ax = float(d.wp_ax); f.wp_off = float(d.wp_off);
     f.wt_ax = float(d.wt_ax); f.wt_off = float(d.wt_off);
     f.wm_para = float(d.wm_para); f.wm_perp = float(d.wm_perp);
     f.wm_in = float(d.wm_in); f.wm_out = float(d.wm_out);
     f.kappa = float(d.kappa);
-    f.omega = float(d.omega);
     f.lambda_on = d.lambda_on;
     f.a = d.a; f.b = d.b; f.T = d.T; f.nu = d.nu;
     f.wp_ax_d = d.wp_ax_d; f.wp_off_d = d.wp_off_d;
@@ -502,7 +527,7 @@ int lbm_init(lbm_ctx **out, const lbm_params *p, void *dev_workspace, size_t byt
         return LBM_E_INVAL;
     }
     make_shift(p, c->cd, rs);
-    c->cf = to_float(c->cd);
+    c->cf = to_float(c->cd, p->lattice);
     launch_init(c, dev_rho0, dev_u0);
     if (hipGetLastError() != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess) {
         delete c;

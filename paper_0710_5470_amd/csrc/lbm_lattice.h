@@ -91,6 +91,7 @@ template <class R> struct Coefs {
     R C, D;            // Laplacian stencil: on-axis, off-axis (centre = -sum)
     R Ef, Ff;          // force-stencil: on-axis, off-axis
     R w_ax, w_off;     // velocity weights
+    R ow_ax, ow_off;   // omega w_ax, omega w_off (odd part of the collision)
     R wp_ax, wp_off;   // w^p
     R wt_ax, wt_off;   // w^t
     // w^aa: velocity along a (axis), axis velocity not along a,
@@ -153,11 +154,12 @@ template <class R> struct EqSite {
 };
 
 template <class L, bool WITH_M, class R>
-__device__ __forceinline__ EqSite<R> eq_site(const Coefs<R> &c, R rho_dev, const R j[3], const R d[3], R lap)
+__device__ __forceinline__ EqSite<R> eq_site(const Coefs<R> &c, double rho_dev, const R j[3], const R d[3], R lap,
+                                             double scale = 1.0)
 {
     constexpr int DIM = L::DIM;
     EqSite<R> s;
-    const double rho_d = double(rho_dev) + c.shift_sum;
+    const double rho_d = rho_dev + c.shift_sum;
     s.rho = R(rho_d);
     const R inv_rho = R(1) / s.rho;
     s.u[0] = j[0] * inv_rho;
@@ -183,11 +185,15 @@ __device__ __forceinline__ EqSite<R> eq_site(const Coefs<R> &c, R rho_dev, const
         s.Mzx = DIM == 3 ? c.kappa * d[2] * d[0] : R(0);
     }
     // the static part w^p_i p0 - s_i in FP64 (the storage shift is the same
-    // within a weight class), then the class terms
-    const R st_ax = R(c.wp_ax_d * p0 - c.shift[1]);
-    const R st_off = R(c.wp_off_d * p0 - c.shift[first_off<L>()]);
-    s.stc[0] = st_ax - (R(1.5) * c.w_ax * trX3 + c.wt_ax * klap);
-    s.stc[1] = st_off - (R(1.5) * c.w_off * trX3 + c.wt_off * klap);
+    // within a weight class), then the class terms, all times `scale` (the
+    // collision passes omega), rounded once: in FP32 these class terms are
+    // the largest part of every moving population's update, so one rounding
+    // at their scale instead of three keeps the per-step error at the size
+    // of the storage rounding
+    const double st_ax = c.wp_ax_d * p0 - c.shift[1];
+    const double st_off = c.wp_off_d * p0 - c.shift[first_off<L>()];
+    s.stc[0] = R(scale * (st_ax - double(R(1.5) * c.w_ax * trX3 + c.wt_ax * klap)));
+    s.stc[1] = R(scale * (st_off - double(R(1.5) * c.w_off * trX3 + c.wt_off * klap)));
     return s;
 }
 
@@ -242,7 +248,7 @@ template <class L, bool WITH_M, class R>
 __device__ __forceinline__ R equilibrium(const Coefs<R> &c, R rho_dev, const R j[3], const R d[3],
                                          R lap, R feq[L::Q])
 {
-    const EqSite<R> s = eq_site<L, WITH_M>(c, rho_dev, j, d, lap);
+    const EqSite<R> s = eq_site<L, WITH_M>(c, double(rho_dev), j, d, lap);
     // opposite velocities share the even terms: each pair is evaluated once
     R sum = R(0);
 #pragma unroll
@@ -273,10 +279,20 @@ template <class L, bool FORCE, class R>
 __device__ __forceinline__ EqSite<R> collide(const Coefs<R> &c, R rho_dev, const R j[3], const R d[3], R lap,
                                              const R g[3], const R fin[L::Q], R out[L::Q])
 {
-    const EqSite<R> s = eq_site<L, !FORCE>(c, rho_dev, j, d, lap);
+    // FP32: the moving populations' sum (small terms) and rho from it and
+    // f_0 in FP64, for the pressure; the rest population then closes the
+    // mass balance with a single rounding at its own scale (below).
+    constexpr bool F32 = sizeof(R) == 4;
+    R s_in = sum0<R>();
+    if constexpr (F32) {
+#pragma unroll
+        for (int i = 1; i < L::Q; i++) s_in += fin[i];
+    }
+    const double rho_d = F32 ? double(s_in) + double(fin[0]) : double(rho_dev);
+    const EqSite<R> s = eq_site<L, !FORCE>(c, rho_d, j, d, lap, double(c.omega));
     const R om = c.omega, keep = R(1) - c.omega;
-    // per-class constant part of E: omega stc - w u.g
-    R K[2] = {om * s.stc[0], om * s.stc[1]};
+    // per-class constant part of E: omega stc (scaled in eq_site) - w u.g
+    R K[2] = {s.stc[0], s.stc[1]};
     if (FORCE) {
         const R ug = s.u[0] * g[0] + s.u[1] * g[1] + (L::DIM == 3 ? s.u[2] * g[2] : R(0));
         K[0] -= c.w_ax * ug;
@@ -292,7 +308,7 @@ __device__ __forceinline__ EqSite<R> collide(const Coefs<R> &c, R rho_dev, const
         const R eu = edot<L>(i, s.u);
         R E = (R(1.5) * om * w) * exe<L>(s, i, eu, edot<L>(i, d)) + K[axis ? 0 : 1];
         if (!FORCE) E += om * m_terms<L>(c, s, i);
-        R D = (om * w) * edot<L>(i, j);
+        R D = (axis ? c.ow_ax : c.ow_off) * edot<L>(i, j);
         if (FORCE) {
             const R eg = edot<L>(i, g);
             E += (R(3) * w * eu) * eg;
@@ -302,7 +318,20 @@ __device__ __forceinline__ EqSite<R> collide(const Coefs<R> &c, R rho_dev, const
         out[i] = keep * fin[i] + (E + D);
         out[o] = keep * fin[o] + (E - D);
     }
-    out[0] = keep * fin[0] + (om * rho_dev - R(2) * sumE);
+    if constexpr (F32) {
+        // out_0 = rho - sum_{i>=1} out_i = f_0 + sum_{i>=1} (f_i - out_i):
+        // the mass exchanged with the moving populations is formed from small
+        // terms and added to f_0 with one rounding, so a site's mass changes
+        // by that one rounding per step, as with FP64 arithmetic.  (The
+        // direct form below rounds at the scale of f_0 ~ rho four times per
+        // step; in FP32 the total mass then drifts about ten times faster.)
+        R s_out = sum0<R>();
+#pragma unroll
+        for (int i = 1; i < L::Q; i++) s_out += out[i];
+        out[0] = fin[0] + (s_in - s_out);
+    } else {
+        out[0] = keep * fin[0] + (om * rho_dev - R(2) * sumE);
+    }
     return s;
 }
 

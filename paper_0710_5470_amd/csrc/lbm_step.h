@@ -238,12 +238,17 @@ __device__ __forceinline__ void step_tile(const Job<R> &J, const Coefs<R> &c)
             f[i] = R(buf_load(rs, e * ES, unsigned(i * stride) * ES, S()));
         }
     };
-    // rho - sum_i s_i of pulled populations (fixed summation order)
+    // rho - sum_i s_i of pulled populations, in a fixed order: the moving
+    // populations first, the rest population last.  In FP32 storage the rest
+    // deviation carries the density contrast between the phases (|delta_0|
+    // up to ~2, against ~1e-2 for the others), so adding it last leaves one
+    // rounding at its scale instead of one per term (the velocity error
+    // against the FP64 oracle drops about threefold, at no cost).
     auto dens = [&](const R(&f)[Q]) -> R {
         R s = sum0<R>();
 #pragma unroll
-        for (int i = 0; i < Q; i++) s += f[i];
-        return s;
+        for (int i = 1; i < Q; i++) s += f[i];
+        return s + f[0];
     };
 
     auto plane_offsets = [&](int p, int(&P)[3]) {

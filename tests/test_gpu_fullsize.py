@@ -12,10 +12,15 @@ the launch plus seeded random sites.
 Tolerances (absolute, on populations of magnitude <= 1):
   FP64 storage: 1e-13 (the oracle and the GPU evaluate the same formulas in
     FP64 from the same inputs; FMA contraction and summation order differ).
-  FP32 storage, FP32 arithmetic: 1e-5, derived: a population is the sum of
-    about 30 rounded FP32 operations whose intermediate magnitudes are at
-    most the van der Waals pressure p0 ~ 4 (ulp 4.8e-7), so the accumulated
-    rounding is below 30 x 0.5 x 4.8e-7 = 7.2e-6.
+  FP32 storage, FP32 arithmetic: 1e-6, derived: the pressure and the static
+    part of the equilibrium are evaluated in FP64, so the FP32 intermediates
+    of a population are bounded by the rest deviation and omega times the
+    density deviation (|delta_0| < 2, omega rho_dev < 2.5); the rest
+    population, the largest, passes through about five FP32 roundings at
+    that scale (the density sum, omega rho_dev, the class sums, the fused
+    keep * delta_0 and the final add, half an ulp of 2.5 each = 1.2e-7) and
+    one rounding when stored: 6 x 1.2e-7 = 7.2e-7 < 1e-6.  The moving
+    populations (|delta_i| ~ 1e-2) are far below that.
 """
 import os
 import sys
@@ -30,8 +35,8 @@ ROOT = os.path.join(os.path.dirname(__file__), "..")
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-CASES = [("d3q19_256_fp32_force", 1e-5), ("d3q19_256_fp64_force", 1e-13),
-         ("d2q9_1024_fp64_eq", 1e-13), ("d2q9_1024_fp32_force", 1e-5)]
+CASES = [("d3q19_256_fp32_force", 1e-6), ("d3q19_256_fp64_force", 1e-13),
+         ("d2q9_1024_fp64_eq", 1e-13), ("d2q9_1024_fp32_force", 1e-6)]
 
 
 def _sites(shape, tile, planes, seed, nrand=1500):

@@ -105,16 +105,20 @@ def test_fp64_scan_overrides_match_oracle():
     assert np.max(np.abs(v_g - v_o)) < 1e-12
 
 
+@pytest.mark.parametrize("storage", [0, 1])
 @pytest.mark.parametrize("q,scheme,shape", [(9, 0, (45, 31)), (9, 1, (45, 31)),
                                             (19, 1, (36, 20, 13)), (19, 0, (36, 20, 13))])
-def test_results_do_not_depend_on_launch_shape(q, scheme, shape):
+def test_results_do_not_depend_on_launch_shape(q, scheme, shape, storage):
+    """Every site's arithmetic is fixed whatever tile and plane chunk compute
+    it (halo densities are recomputed in the same order), so the state is
+    bitwise the same for every launch shape, in FP64 and in FP32 storage."""
     lbm = _lbm()
-    gp, _ = _pair(q, scheme, lbm.STORE_F64, shape, tau=0.8)
+    gp, _ = _pair(q, scheme, storage, shape, tau=0.8)
     rho0 = _rho_drop(shape, 0.56, noise=0.02)
     ref = None
     for tile in range(lbm.lbm_tile_count(q)):
         for planes in (1, 3, 64):
-            _say("launch shape", q, scheme, shape, tile, planes)
+            _say("launch shape", q, scheme, shape, storage, tile, planes)
             sim = lbm.Simulation(gp, rho0)
             sim.set_launch(tile, planes)
             sim.step(25)
@@ -170,12 +174,34 @@ def test_fp32_storage_f64_math_meets_stated_tolerance(q, scheme, shape, steps):
 @pytest.mark.parametrize("q,scheme,shape,steps", FP32_CASES)
 def test_fp32_storage_f32_math_within_derived_tolerance(q, scheme, shape, steps):
     """FP32 storage and FP32 arithmetic: 1e-5 relative on rho; the velocity
-    is held to 1e-6 absolute, the tolerance derived from the FP32 rounding of
-    the van der Waals pressure components (rho T/(1-b rho) ~ a rho^2 ~ 4 in
-    the liquid, ulp ~ 5e-7) that enter the force balance every step."""
+    is held to 2e-8 absolute.  The velocity error comes from roundings of
+    the rest deviation delta_0 (|delta_0| < 2, half an ulp 1.2e-7), which
+    carries the density contrast between the phases and acts on the flow
+    through the pressure and kappa rho lap rho terms.  FP64 arithmetic on the
+    same storage rounds it once per site and step (its storage) and stays
+    below 1e-8 (the test above); FP32 arithmetic adds per site and step one
+    rounding of the same size in the LDS density plane and two in the rest
+    population's collision, about twice the error in quadrature: 2e-8."""
     err_r, err_v = _fp32_case(q, scheme, shape, steps, compute=0)
     assert err_r < 1e-5
-    assert err_v < 1e-6
+    assert err_v < 2e-8
+
+
+def test_fp32_d3q19_force_64cubed_500_steps():
+    """The D3Q19 forcing workload's physics (T = 0.56, kappa = 0.02,
+    tau = 0.8, a drop with 0.01 noise) on a 64^3 cut-down, 500 steps, FP32
+    shifted storage with FP32 arithmetic against the FP64 oracle."""
+    lbm = _lbm()
+    shape = (64, 64, 64)
+    gp, op = _pair(19, 1, lbm.STORE_F32_SHIFTED, shape, tau=0.8, kappa=0.02)
+    rho0 = _rho_drop(shape, 0.56, R=12.0, noise=0.01, seed=3)
+    f_g, r_g, v_g, f_o, r_o, v_o = _run_both(gp, op, rho0, 500)
+    err_r = np.max(np.abs(r_g - r_o) / r_o)
+    err_v = np.max(np.abs(v_g - v_o))
+    _say("64^3 FP32 force 500 steps: err rho %.3e vel %.3e (max|v| %.3e)"
+         % (err_r, err_v, np.sqrt((v_o ** 2).sum(0)).max()))
+    assert err_r < 1e-5
+    assert err_v < 2e-8
 
 
 def test_fp32_literal_weight_shift():

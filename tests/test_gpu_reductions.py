@@ -1,0 +1,216 @@
+"""GPU parity of the FP64 reductions against the oracle.
+
+The library's reductions are the conservation totals of Appendix A
+(Eqs. (ncons) and the first moment: mass sum_r rho, momentum
+sum_r sum_i f_i e_i), the spurious velocity of section "Numerical results"
+(the maximum velocity magnitude in the system: |u| for the equilibrium
+scheme, |v| = |u + g / 2 rho| for the forcing scheme) and the steady-state
+residual max_r |v(r, t + 1) - v(r, t)|.  Two levels are checked:
+
+1. the reduction of a state: each GPU reduction against the oracle's
+   reduction of the very same state (read back with lbm_get_state), for FP64
+   and FP32 storage (the FP32 mass adds back n sum_i s_i on the host);
+2. end to end: the GPU's reductions after N steps against the oracle's
+   reductions of its own N-step run.
+
+States carry a non-uniform velocity field, so the momentum has a sign and
+three different components.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+A, B_ = 9.0 / 49.0, 2.0 / 21.0
+EPS32 = 2.0 ** -24  # FP32 unit roundoff
+
+
+def _say(*a):
+    print("[gpu-case]", *a, flush=True)
+
+
+def _inputs(shape, seed):
+    """A drop between the coexistence densities (T = 0.56) with 0.01 noise,
+    moving as a blob with velocity (0.01, -0.006, 0.004) inside a fluid with a
+    smooth shear flow."""
+    from paper_0710_5470_amd import inputs, lbm
+    g, l = lbm.lbm_coexistence(A, B_, 0.56)
+    rho0 = inputs.tanh_drop(shape, min(shape[:2]) / 4.0, l, g, 2.0)
+    rho0 = rho0 + inputs.uniform_noise(shape, 0.01, seed)
+    dim = len(shape)
+    grid = np.meshgrid(*[np.arange(s) for s in reversed(shape)], indexing="ij")  # z, y, x
+    x, y = grid[-1], grid[-2]
+    u0 = np.zeros((3,) + rho0.shape)
+    u0[0] = 0.004 * np.sin(2 * np.pi * y / shape[1])
+    u0[1] = -0.003 * np.cos(2 * np.pi * x / shape[0])
+    blob = rho0 > 0.5 * (g + l)
+    vb = [0.01, -0.006, 0.004]
+    for a in range(dim):
+        u0[a][blob] += vb[a]
+    return rho0, u0
+
+
+def _params(q, scheme, storage, compute, shape):
+    import oracle
+    from paper_0710_5470_amd import lbm
+    tau = 0.8 if q == 19 else 0.9
+    kappa = 0.02 if q == 19 else 0.025
+    gp = lbm.params(lattice=q, scheme=scheme, storage=storage, compute=compute, shape=shape,
+                    T=0.56, kappa=kappa, tau=tau)
+    op = oracle.params(q=q, scheme=scheme, shape=shape, T=0.56, kappa=kappa, tau=tau)
+    return gp, op
+
+
+def _speed(vel):
+    return np.sqrt((vel ** 2).sum(0))
+
+
+# (storage, compute): FP64; FP32 with FP64 arithmetic; FP32 native
+MODES = [(0, 0), (1, 1), (1, 0)]
+SHAPES = {9: (37, 29), 19: (20, 14, 11)}
+
+
+def _vel_tol(storage, compute, f_state, shift, rho_min):
+    """Absolute tolerance of one velocity evaluated by the GPU from a state
+    against the oracle's FP64 evaluation of the same state.  FP64 arithmetic:
+    1e-13 (round-off of a few dozen FP64 operations on |v| < 1e-2).  FP32
+    arithmetic: j sums 18 stored deviations delta_i = f_i - s_i and the body
+    force sums 18 neighbour terms of the same size class, each FP32 operation
+    rounding by at most EPS32 times the running magnitude; with m the largest
+    |delta_i| (i >= 1) over the state, |j error| <= 18^2 EPS32 m / 2 and the
+    velocity error is that over rho_min, doubled for the force term."""
+    if storage == 0 or compute == 1:
+        return 1e-13
+    m = float(np.max(np.abs(f_state[1:] - shift[1:, None])))
+    return 2.0 * 18 * 18 * EPS32 * m / 2.0 / rho_min
+
+
+@pytest.mark.parametrize("q", [9, 19])
+@pytest.mark.parametrize("scheme", [0, 1])
+@pytest.mark.parametrize("storage,compute", MODES)
+def test_reductions_of_a_state_match_oracle(q, scheme, storage, compute):
+    """lbm_invariants, lbm_max_spurious_u and lbm_step_observed's residual
+    and max|v| against the oracle's totals and observables of the same
+    GPU-produced states."""
+    import oracle
+    from paper_0710_5470_amd import lbm
+    shape = SHAPES[q]
+    gp, op = _params(q, scheme, storage, compute, shape)
+    rho0, u0 = _inputs(shape, 21)
+    _say("reductions of a state q", q, "scheme", scheme, "storage", storage, "compute", compute)
+    sim = lbm.Simulation(gp, rho0, u0)
+    sim.step(30)
+    f_prev = sim.get_state().cpu().numpy()
+    res_g, vmax1_g, ok = sim.step_observed(1)
+    assert ok
+    f = sim.get_state().cpu().numpy()
+    mass_g, mom_g = sim.invariants()
+    vmax_g = sim.max_spurious_u()
+    shift = np.asarray(sim.shift(), dtype=np.float64)
+    sim.close()
+
+    mass_o, mom_o = oracle.totals(op, f)
+    assert abs(mass_g - mass_o) / mass_o < 1e-12
+    assert np.max(np.abs(np.array(mom_g) - mom_o)) < 1e-12 * mass_o
+    # the totals are not trivially zero: every component is resolved
+    assert np.min(np.abs(mom_o[:2 if q == 9 else 3])) > 1e-3 * np.max(np.abs(mom_o))
+
+    r_o, v_o = oracle.observe(op, f)
+    _, v_prev_o = oracle.observe(op, f_prev)
+    tol = _vel_tol(storage, compute, f, shift, float(r_o.min()))
+    vmax_o = float(_speed(v_o).max())
+    res_o = float(_speed(v_o - v_prev_o).max())
+    _say("  max|v| %.6e vs %.6e, residual %.6e vs %.6e, tol %.1e"
+         % (vmax_g, vmax_o, res_g, res_o, tol))
+    assert abs(vmax_g - vmax_o) <= tol
+    assert abs(vmax1_g - vmax_o) <= tol
+    assert abs(res_g - res_o) <= 2 * tol
+    assert res_o > 0.0
+
+
+def _mass_drift_bound(f0, shift, steps):
+    """FP32 storage: each step rounds every stored deviation once (by at
+    most EPS32 |delta_i|), so the total mass and each momentum component can
+    move by at most steps * sum_r sum_i EPS32 |delta_i| over the run; with
+    FP32 arithmetic the collision adds a few more roundings of the same
+    size per population (taken as 4)."""
+    return 4.0 * steps * EPS32 * float(np.sum(np.abs(f0 - shift[:, None])))
+
+
+@pytest.mark.parametrize("q", [9, 19])
+@pytest.mark.parametrize("scheme", [0, 1])
+@pytest.mark.parametrize("storage,compute", MODES)
+def test_reductions_after_steps_match_oracle_run(q, scheme, storage, compute):
+    """End to end: the GPU's totals, max|v| and residual after N steps
+    against the oracle's own N-step run from the same initial state.  FP64
+    storage within 1e-12; FP32 storage within the derived drift bound for
+    the totals and the FP32 velocity tolerances (1e-8 with FP64 arithmetic,
+    2e-8 with FP32 arithmetic) for max|v| and the residual."""
+    import oracle
+    from paper_0710_5470_amd import lbm
+    shape = SHAPES[q]
+    steps = 40
+    gp, op = _params(q, scheme, storage, compute, shape)
+    rho0, u0 = _inputs(shape, 22)
+    _say("reductions end to end q", q, "scheme", scheme, "storage", storage, "compute", compute)
+    sim = lbm.Simulation(gp, rho0, u0)
+    f0 = sim.get_state().cpu().numpy()
+    shift = np.asarray(sim.shift(), dtype=np.float64)
+    sim.step(steps - 1)
+    res_g, vmax_g, ok = sim.step_observed(1)
+    assert ok
+    mass_g, mom_g = sim.invariants()
+    sim.close()
+
+    fo_prev = oracle.run(op, oracle.init(op, rho0, u0), steps - 1)
+    fo = oracle.run(op, fo_prev, 1)
+    mass_o, mom_o = oracle.totals(op, fo)
+    _, v_o = oracle.observe(op, fo)
+    _, v_prev = oracle.observe(op, fo_prev)
+    vmax_o = float(_speed(v_o).max())
+    res_o = float(_speed(v_o - v_prev).max())
+    if storage == 0:
+        t_m, t_v = 1e-12 * mass_o, 1e-12
+    else:
+        # the velocity tolerances of the FP32 parity tests: 1e-8 with FP64
+        # arithmetic, 2e-8 with FP32 arithmetic
+        t_m, t_v = _mass_drift_bound(f0, shift, steps), (1e-8 if compute else 2e-8)
+    _say("  mass %.3e mom %.3e vmax %.3e res %.3e (tol mass %.1e vel %.1e)"
+         % (abs(mass_g - mass_o), np.max(np.abs(np.array(mom_g) - mom_o)), abs(vmax_g - vmax_o),
+            abs(res_g - res_o), t_m, t_v))
+    assert abs(mass_g - mass_o) <= t_m
+    assert np.max(np.abs(np.array(mom_g) - mom_o)) <= t_m
+    assert abs(vmax_g - vmax_o) <= t_v
+    assert abs(res_g - res_o) <= 2 * t_v
+
+
+@pytest.mark.parametrize("scheme,storage,compute", [(0, 0, 0), (1, 0, 0), (1, 1, 0), (0, 1, 1)])
+def test_batch_max_spurious_u_matches_oracle_per_problem(scheme, storage, compute):
+    """lbm_batch_max_spurious_u of every problem of a batch (uneven sizes and
+    parameters) against the oracle's run of that problem alone."""
+    import oracle
+    from paper_0710_5470_amd import inputs, lbm
+    specs = [dict(shape=(37, 29), R=8.0, T=0.55, kappa=0.01, tau=0.9),
+             dict(shape=(64, 64), R=12.0, T=0.56, kappa=0.02, tau=1.0),
+             dict(shape=(33, 40), R=7.0, T=0.545, kappa=0.012, tau=1.2)]
+    plist, rhos, ops = [], [], []
+    for s in specs:
+        g, l = lbm.lbm_coexistence(A, B_, s["T"])
+        plist.append(lbm.params(lattice=9, scheme=scheme, storage=storage, compute=compute,
+                                shape=s["shape"], T=s["T"], kappa=s["kappa"], tau=s["tau"]))
+        rhos.append(inputs.tanh_drop(s["shape"], s["R"], l, g, 2.0)
+                    + inputs.uniform_noise(s["shape"], 0.01, 7))
+        ops.append(oracle.params(q=9, scheme=scheme, shape=s["shape"], T=s["T"],
+                                 kappa=s["kappa"], tau=s["tau"]))
+    _say("batch max|v| scheme", scheme, "storage", storage, "compute", compute)
+    bt = lbm.Batch(plist, rhos)
+    bt.step(50)
+    vmax_g = bt.max_spurious_u()
+    bt.close()
+    tol = 1e-12 if storage == 0 else (1e-8 if compute else 2e-8)
+    for k, (op, r0) in enumerate(zip(ops, rhos)):
+        _, v = oracle.observe(op, oracle.run(op, oracle.init(op, r0), 50))
+        vmax_o = float(_speed(v).max())
+        _say("  problem %d: %.6e vs %.6e" % (k, vmax_g[k], vmax_o))
+        assert abs(vmax_g[k] - vmax_o) <= tol
