@@ -275,9 +275,12 @@ __device__ __forceinline__ R equilibrium(const Coefs<R> &c, R rho_dev, const R j
 // (F_0 = -sum_{i>=1} F_i and f_0^eq = rho - sum_{i>=1} f_i^eq).  omega is
 // folded into the per-class terms.  g: body force (FORCE only).  Returns the
 // site quantities (rho, u) for the caller's observables.
-template <class L, bool FORCE, class R>
+// emit(i, v) receives each collided population as soon as it is final (the
+// pair i, opp(i) together, the rest population last), so that callers can
+// store it at once instead of keeping all Q values live.
+template <class L, bool FORCE, class R, class Emit>
 __device__ __forceinline__ EqSite<R> collide(const Coefs<R> &c, R rho_dev, const R j[3], const R d[3], R lap,
-                                             const R g[3], const R fin[L::Q], R out[L::Q])
+                                             const R g[3], const R fin[L::Q], Emit &&emit)
 {
     // FP32: the moving populations' sum (small terms) and rho from it and
     // f_0 in FP64, for the pressure; the rest population then closes the
@@ -299,6 +302,7 @@ __device__ __forceinline__ EqSite<R> collide(const Coefs<R> &c, R rho_dev, const
         K[1] -= c.w_off * ug;
     }
     R sumE = sum0<R>();
+    R s_out = sum0<R>();
 #pragma unroll
     for (int i = 1; i < L::Q; i++) {
         if (opp<L>(i) < i) continue;
@@ -315,8 +319,14 @@ __device__ __forceinline__ EqSite<R> collide(const Coefs<R> &c, R rho_dev, const
             D += w * eg;
         }
         sumE += E;
-        out[i] = keep * fin[i] + (E + D);
-        out[o] = keep * fin[o] + (E - D);
+        const R oi = keep * fin[i] + (E + D);
+        const R oo = keep * fin[o] + (E - D);
+        if constexpr (F32) {
+            s_out += oi;
+            s_out += oo;
+        }
+        emit(i, oi);
+        emit(o, oo);
     }
     if constexpr (F32) {
         // out_0 = rho - sum_{i>=1} out_i = f_0 + sum_{i>=1} (f_i - out_i):
@@ -325,12 +335,9 @@ __device__ __forceinline__ EqSite<R> collide(const Coefs<R> &c, R rho_dev, const
         // by that one rounding per step, as with FP64 arithmetic.  (The
         // direct form below rounds at the scale of f_0 ~ rho four times per
         // step; in FP32 the total mass then drifts about ten times faster.)
-        R s_out = sum0<R>();
-#pragma unroll
-        for (int i = 1; i < L::Q; i++) s_out += out[i];
-        out[0] = fin[0] + (s_in - s_out);
+        emit(0, fin[0] + (s_in - s_out));
     } else {
-        out[0] = keep * fin[0] + (om * rho_dev - R(2) * sumE);
+        emit(0, keep * fin[0] + (om * rho_dev - R(2) * sumE));
     }
     return s;
 }

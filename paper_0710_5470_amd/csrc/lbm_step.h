@@ -9,14 +9,13 @@
 // One workgroup owns a TX x TY tile of a plane and marches through `cp`
 // consecutive planes (D2Q9: rows along y, TY = 1; D3Q19: xy-planes along z).
 // Densities (as rho - sum_i s_i) of the tile plus an H-site halo (H = 1 for
-// the equilibrium scheme, H = 2 for the forcing scheme, whose force needs
-// gradients one site beyond the tile) live in an LDS ring; for the forcing
-// scheme a second ring holds the gradient of rho on the tile plus one site.
-// Each thread keeps the pulled populations of its own site in registers from
-// the plane where they are loaded (H planes ahead) until that plane is
-// collided.  Halo densities are recomputed from populations owned by
-// neighbouring tiles (they come from L2 / MALL when the neighbours run
-// concurrently, which the XCD-aware workgroup order encourages).
+// the equilibrium scheme, below; H = 2 for the forcing scheme, lbm_force.h)
+// live in an LDS ring of planes.  Each thread keeps the pulled populations
+// of its own site in registers from the plane where they are loaded (H + 1
+// planes ahead of the collision) until that plane is collided.  Halo
+// densities are recomputed from populations owned by neighbouring tiles
+// (they come from L2 / MALL when the neighbours run concurrently, which the
+// XCD-aware workgroup order encourages).
 //
 // Population arrays are read and written through one buffer resource per
 // array (32-bit byte offsets, hardware range check); the direction's offset
@@ -96,20 +95,6 @@ template <class L, int SCHEME, class S> constexpr int batch_waves_per_eu()
     return (L::DIM == 2 && SCHEME == SCHEME_EQ && sizeof(S) == 8) ? 3 : 1;
 }
 
-// Planes ahead of the density front at which the forcing scheme loads its
-// halo populations: 1, 2, or 0 = 2 for FP64 arithmetic and 1 for FP32.
-// Own-site loads (from HBM) are always one plane ahead and issued first;
-// with 2, the halo loads (mostly L2 hits) for the plane after next go out
-// behind them, so the wait for the own loads leaves them in flight.  This
-// costs 19 registers and a load from every thread, also those without a
-// halo site: it pays where the kernel computes in FP64, which already runs
-// one wave per SIMD (D3Q19 256^3: 1.626 against 1.688 ms per step for FP64
-// storage, 1.08 against 1.18 ms for FP32 storage with FP64 arithmetic), and
-// not for FP32 arithmetic (0.747 against 0.684 ms).
-#ifndef LBM_HALO_AHEAD
-#define LBM_HALO_AHEAD 0
-#endif
-
 // One workgroup's share of a step: the tile at (x0, y0) of planes
 // [p0, p0 + npl) of one problem.
 template <class R> struct Job {
@@ -125,42 +110,27 @@ template <class R> struct Job {
     int write_pops, observe;
 };
 
-template <class L, int SCHEME, class S, class R, int TX, int TY>
-__device__ __forceinline__ void step_tile(const Job<R> &J, const Coefs<R> &c)
+// The equilibrium scheme (Eq. (equilibrium)): gradients and Laplacian of
+// the density are needed one site away, so the ring holds the tile plus a
+// 1-site halo and the own populations stay in registers for H + 1 = 2
+// planes after their density is stored.
+template <class L, class S, class R, int TX, int TY>
+__device__ __forceinline__ void eq_tile(const Job<R> &J, const Coefs<R> &c)
 {
     constexpr int Q = L::Q;
-    constexpr bool FORCE = SCHEME == SCHEME_FORCE;
-    constexpr int H = FORCE ? 2 : 1;            // density halo
+    constexpr int H = 1;                        // density halo
     constexpr int HY = L::DIM == 3 ? H : 0;     // in-plane y halo
     constexpr int TXH = TX + 2 * H, TYH = TY + 2 * HY;
     constexpr int PL = TXH * TYH;               // LDS sites per density plane
-    // Density ring depth: planes lc - 1 .. lc + H + 1 are live (5 for the
-    // forcing scheme, 4 for the equilibrium scheme).  RP2 rounds the rings
-    // up to powers of two, so that a ring slot is a mask, not a division:
-    // faster for FP64 storage and D2Q9; for D3Q19 FP32 the extra uniform
-    // address terms push the kernel to 256 VGPRs and it runs 2.5 % slower.
-    constexpr bool RP2 = sizeof(S) == 8 || L::DIM == 2;
-    constexpr int NR = FORCE ? (RP2 ? 8 : 5) : 4;
-    constexpr int GY = L::DIM == 3 ? 1 : 0;     // gradient ring in-plane y halo
-    constexpr int TXG = TX + 2, TYG = TY + 2 * GY;
-    constexpr int GPL = TXG * TYG;
+    // density ring: planes lc - 1 .. lc + 2 are live; four slots, so a ring
+    // slot is a mask, not a division
+    constexpr int NR = 4;
     constexpr int NT = TX * TY;
     constexpr int NHALO = 2 * HY * TXH + 2 * H * TY;
     constexpr int NHT = (NHALO + NT - 1) / NT;  // halo sites per thread
     constexpr unsigned ES = sizeof(S);
 
     __shared__ R rho_s[NR * PL];
-    // Gradient ring (forcing scheme): per site of the tile + 1 ring, the
-    // gradient of rho and, in FP32, the tensor T_ab = kappa (d_a d_b -
-    // delta_ab |d|^2 / 2) whose stencil divergence is the body force (3D:
-    // xx, yy, zz, xy, xz, yz; 2D: xx, xy, as T_yy = -T_xx).  Precomputing T
-    // once per ring site replaces the per-neighbour products of the force
-    // sum; in FP64 the ring would not fit the LDS, so T is formed there on
-    // the fly from the stored gradient.
-    constexpr bool TT = FORCE && sizeof(R) == 4;
-    constexpr int NG = TT ? (L::DIM == 3 ? 9 : 4) : 3;
-    constexpr int NGR = RP2 ? 4 : 3;  // gradient ring depth (3 planes live)
-    __shared__ R grad_s[FORCE ? NGR * NG * GPL : 1];
 
     const S *src = static_cast<const S *>(J.src);
     S *dst = static_cast<S *>(J.dst);
@@ -223,11 +193,8 @@ __device__ __forceinline__ void step_tile(const Job<R> &J, const Coefs<R> &c)
     // for k = 0..H; fr[H + 1] receives the next plane, whose loads are in
     // flight while the current plane is collided (software pipelining: the
     // memory latency of plane p + H + 1 overlaps the arithmetic of plane p).
-    // hr holds the in-flight halo populations, HA planes deep.
-    constexpr int HA =
-        FORCE && (LBM_HALO_AHEAD == 2 || (LBM_HALO_AHEAD == 0 && sizeof(R) == 8)) ? 2 : 1;
     R fr[H + 2][Q];
-    R hr[HA][NHT][Q];
+    R hr[NHT][Q];
 
     // issue the Q loads of the populations arriving at the site with offsets
     // (Xo, Yo) in the plane whose wrapped neighbour-plane offsets are P
@@ -262,113 +229,48 @@ __device__ __forceinline__ void step_tile(const Job<R> &J, const Coefs<R> &c)
     };
 
     // local plane lp is global plane p0 - H + lp: issue the loads of its own
-    // site (into f) or of its halo sites (into h); store their densities
-    // (pg: the global plane index of lp, wrapped)
+    // site (into f) or of its halo sites; store their densities (pg: the
+    // global plane index of lp, wrapped)
     auto load_own = [&](int pg, R(&f)[Q]) {
         int P[3];
         plane_offsets(pg, P);
         pull(X, Y, P, f);
     };
-    auto load_halo = [&](int pg, R(&h)[NHT][Q]) {
+    auto load_halo = [&](int pg) {
         int P[3];
         plane_offsets(pg, P);
-        // With HA = 2 threads without a halo site load a valid dummy site
-        // (lx = ly = 0) and ignore it: without a branch the compiler can
-        // count these loads and leave them in flight at the next wait.
 #pragma unroll
         for (int s = 0; s < NHT; s++)
-            if (HA == 2 || hv[s]) pull(hX[s], hY[s], P, h[s]);
+            if (hv[s]) pull(hX[s], hY[s], P, hr[s]);
     };
-    auto store_rho = [&](int lp, const R(&f)[Q], const R(&h)[NHT][Q]) {
+    auto store_rho = [&](int lp, const R(&f)[Q]) {
         R *ring = rho_s + (unsigned(lp) % NR) * PL;
         ring[(ty + HY) * TXH + tx + H] = dens(f);
 #pragma unroll
         for (int s = 0; s < NHT; s++)
-            if (hv[s]) ring[hL[s]] = dens(h[s]);
-    };
-
-    // gradient of rho on the tile + 1 ring of local plane lp (forcing only)
-    auto grad_at = [&](int lp, int comp, int lx, int ly) -> R & {
-        return grad_s[((unsigned(lp) % NGR) * NG + comp) * GPL + ly * TXG + lx];
-    };
-    // component index of T_ab in the ring (TT only); 2D T_yy is -T_xx
-    auto t_comp = [](int a, int b) constexpr -> int {
-        if (L::DIM == 2) return a == b ? 2 : 3;
-        if (a == b) return 3 + a;
-        const int lo = a < b ? a : b, hi = a < b ? b : a;
-        return lo == 0 ? (hi == 1 ? 6 : 7) : 8;
-    };
-    auto t_at = [&](int lp, int a, int b, int lx, int ly) -> R {
-        const R v = grad_at(lp, t_comp(a, b), lx, ly);
-        return (L::DIM == 2 && a == 1 && b == 1) ? -v : v;
-    };
-    // stencil gradient of the density plane ring at local site (rx, ry) of
-    // local plane lp, summed per weight class: d_a = A sum_axis e_a rho +
-    // B sum_off e_a rho
-    auto gradient = [&](int lp, int rx, int ry, R(&d)[3]) {
-        R sa[3] = {sum0<R>(), sum0<R>(), sum0<R>()}, so[3] = {sum0<R>(), sum0<R>(), sum0<R>()};
-#pragma unroll
-        for (int i = 1; i < Q; i++) {
-            R r = rho_at(lp + op<L>(i), rx + ox<L>(i), ry + oy<L>(i));
-            R *acc = nnz<L>(i) == 1 ? sa : so;
-            if (L::ex[i]) acc[0] += R(L::ex[i]) * r;
-            if (L::ey[i]) acc[1] += R(L::ey[i]) * r;
-            if (L::ez[i]) acc[2] += R(L::ez[i]) * r;
-        }
-#pragma unroll
-        for (int a = 0; a < 3; a++) d[a] = a < L::DIM ? c.A * sa[a] + c.B * so[a] : R(0);
-    };
-    auto fill_grad = [&](int lp) {
-        for (int k = tid; k < GPL; k += NT) {
-            const int lx = k % TXG, ly = k / TXG;
-            const int rx = lx + (H - 1), ry = ly + (HY - GY);
-            R d[3];
-            gradient(lp, rx, ry, d);
-            grad_at(lp, 0, lx, ly) = d[0];
-            grad_at(lp, 1, lx, ly) = d[1];
-            if (!TT || L::DIM == 3) grad_at(lp, 2, lx, ly) = d[2];
-            if constexpr (TT) {
-                const R h = R(0.5) * (d[0] * d[0] + d[1] * d[1] + (L::DIM == 3 ? d[2] * d[2] : R(0)));
-#pragma unroll
-                for (int a = 0; a < L::DIM; a++)
-#pragma unroll
-                    for (int b = a; b < L::DIM; b++) {
-                        if (L::DIM == 2 && a == 1 && b == 1) continue;
-                        grad_at(lp, t_comp(a, b), lx, ly) = c.kappa * (d[a] * d[b] - (a == b ? h : R(0)));
-                    }
-            }
-        }
+            if (hv[s]) ring[hL[s]] = dens(hr[s]);
     };
 
     // prologue: densities of planes p0-H .. p0+H (own populations of
-    // p0 .. p0+H kept in fr[0..H]), gradients of p0-1, p0
-    // (uniform across the workgroup, and marked so for the compiler; where
-    // scalar registers run short, as in the D3Q19 FP32 forcing kernel, it
-    // still keeps these values in vector registers)
+    // p0 .. p0+H kept in fr[0..H])
+    // (uniform across the workgroup, and marked so for the compiler)
     auto gplane = [&](int lp) { return __builtin_amdgcn_readfirstlane(wrapg(p0 - H + lp, np)); };
     for (int lp = 0; lp < H; lp++) {
         load_own(gplane(lp), fr[H + 1]);
-        load_halo(gplane(lp), hr[0]);
-        store_rho(lp, fr[H + 1], hr[0]);
+        load_halo(gplane(lp));
+        store_rho(lp, fr[H + 1]);
     }
 #pragma unroll
     for (int s = 0; s <= H; s++) {
         load_own(gplane(H + s), fr[s]);
-        load_halo(gplane(H + s), hr[0]);
-        store_rho(H + s, fr[s], hr[0]);
-    }
-    // with HA = 2 the halo of plane 2H + 1 (the first front) is loaded here
-    if (HA == 2 && npl > 1) load_halo(gplane(2 * H + 1), hr[0]);
-    __syncthreads();
-    if (FORCE) {
-        fill_grad(1);
-        fill_grad(2);
+        load_halo(gplane(H + s));
+        store_rho(H + s, fr[s]);
     }
 
-    // Global indices (wrapped) of the plane collided, of the own-site load
-    // front and of the halo load front, advanced by one plane per iteration
-    // (uniform values: a compare and select, not a division).
-    int pg_c = gplane(H), pg_f = gplane(2 * H + 1), pg_h = gplane(2 * H + HA);
+    // Global indices (wrapped) of the plane collided and of the load front,
+    // advanced by one plane per iteration (uniform values: a compare and
+    // select, not a division).
+    int pg_c = gplane(H), pg_f = gplane(2 * H + 1);
     auto advance = [&](int &pg) { pg = pg + 1 == np ? 0 : pg + 1; };
 
     // One plane.  The register ring is indexed at compile time: plane H + k
@@ -379,18 +281,13 @@ __device__ __forceinline__ void step_tile(const Job<R> &J, const Coefs<R> &c)
         constexpr int RING = H + 2;
         constexpr int C0 = decltype(phase)::value % RING;            // plane lc
         constexpr int CN = (decltype(phase)::value + H + 1) % RING;  // plane lc + H + 1
-        constexpr int HB = decltype(phase)::value % HA;               // halo of plane lc + H + 1
-        constexpr int HN = (decltype(phase)::value + 1) % HA;         // halo of plane lc + H + HA
         const int lc = H + k;  // local index of the plane collided now
         const bool more = decltype(always_more)::value || k + 1 < npl;
-        const bool more_h = decltype(always_more)::value || k + HA < npl;
-        if (more) load_own(pg_f, fr[CN]);  // plane lc + H + 1, consumed after the collision
-        if (more_h) load_halo(pg_h, hr[HN]);  // plane lc + H + HA
-        __syncthreads();  // densities up to plane lc + H are in LDS
-        if (FORCE) {
-            fill_grad(lc + 1);
-            __syncthreads();
+        if (more) {
+            load_own(pg_f, fr[CN]);  // plane lc + H + 1, consumed after the collision
+            load_halo(pg_f);
         }
+        __syncthreads();  // densities up to plane lc + H are in LDS
         const int lx = tx + H, ly = ty + HY;
         const R rho_dev = rho_at(lc, lx, ly);
         R j[3] = {sum0<R>(), sum0<R>(), L::DIM == 3 ? sum0<R>() : R(0)};
@@ -400,86 +297,40 @@ __device__ __forceinline__ void step_tile(const Job<R> &J, const Coefs<R> &c)
             if (L::ey[i]) j[1] += R(L::ey[i]) * fr[C0][i];
             if (L::ez[i]) j[2] += R(L::ez[i]) * fr[C0][i];
         }
-        R d[3] = {R(0), R(0), R(0)};
+        // gradient (per weight class, Eq. (xderiv)) and Laplacian
+        // (Eq. (laplace)) from the density ring
+        R sa[3] = {sum0<R>(), sum0<R>(), sum0<R>()}, so[3] = {sum0<R>(), sum0<R>(), sum0<R>()};
         R lap = sum0<R>();
 #pragma unroll
         for (int i = 1; i < Q; i++) {
-            R r = rho_at(lc + op<L>(i), lx + ox<L>(i), ly + oy<L>(i));
+            const R r = rho_at(lc + op<L>(i), lx + ox<L>(i), ly + oy<L>(i));
+            R *acc = nnz<L>(i) == 1 ? sa : so;
+            if (L::ex[i]) acc[0] += R(L::ex[i]) * r;
+            if (L::ey[i]) acc[1] += R(L::ey[i]) * r;
+            if (L::ez[i]) acc[2] += R(L::ez[i]) * r;
             lap += coef_lap<L>(c, i) * (r - rho_dev);
         }
-        if (!FORCE) gradient(lc, lx, ly, d);
-        R g[3] = {R(0), R(0), R(0)};
-        if (FORCE) {
-            const int gx1 = tx + 1, gy1 = ty + GY;
-            d[0] = grad_at(lc, 0, gx1, gy1);
-            d[1] = grad_at(lc, 1, gx1, gy1);
-            d[2] = L::DIM == 3 ? grad_at(lc, 2, gx1, gy1) : R(0);
-            // g_a = -sum_i c_i sum_b e_ib T_ab(r + e_i), T_ab = kappa (dn_a
-            // dn_b - delta_ab |dn|^2 / 2) with dn the gradient at r + e_i:
-            // the divergence of the kappa part of the pressure tensor,
-            // Eq. (pt), with the force stencil
-            if constexpr (TT) {
-                // the T terms summed per weight class (one coefficient each),
-                // then scaled
-                R ga[2][3];
+        R d[3];
 #pragma unroll
-                for (int a = 0; a < 3; a++) ga[0][a] = ga[1][a] = sum0<R>();
-#pragma unroll
-                for (int i = 1; i < Q; i++) {
-                    const int lp = lc + op<L>(i), qx = gx1 + ox<L>(i), qy = gy1 + oy<L>(i);
-                    R *acc = nnz<L>(i) == 1 ? ga[0] : ga[1];
-#pragma unroll
-                    for (int a = 0; a < L::DIM; a++)
-#pragma unroll
-                        for (int b2 = 0; b2 < L::DIM; b2++)
-                            if (ecomp<L>(i, b2)) acc[a] += R(ecomp<L>(i, b2)) * t_at(lp, a, b2, qx, qy);
-                }
-#pragma unroll
-                for (int a = 0; a < L::DIM; a++) g[a] = c.Ef * ga[0][a] + c.Ff * ga[1][a];
-            } else {
-#pragma unroll
-                for (int a = 0; a < L::DIM; a++) g[a] = sum0<R>();
-#pragma unroll
-                for (int i = 1; i < Q; i++) {
-                    const int lp = lc + op<L>(i), qx = gx1 + ox<L>(i), qy = gy1 + oy<L>(i);
-                    const R cf = coef_force<L>(c, i);
-                    R n[3] = {grad_at(lp, 0, qx, qy), grad_at(lp, 1, qx, qy),
-                              L::DIM == 3 ? grad_at(lp, 2, qx, qy) : R(0)};
-                    R de = edot<L>(i, n);
-                    R dd = R(0.5) * (n[0] * n[0] + n[1] * n[1] + (L::DIM == 3 ? n[2] * n[2] : R(0)));
-#pragma unroll
-                    for (int a = 0; a < L::DIM; a++) {
-                        // n_a (e.n) - e_a |n|^2 / 2, one fused rounding
-                        const int e = ecomp<L>(i, a);
-                        const R t = e > 0 ? n[a] * de - dd : (e < 0 ? n[a] * de + dd : n[a] * de);
-                        g[a] += cf * t;
-                    }
-                }
-            }
-            const R kg = TT ? R(-1) : -c.kappa;
-            g[0] *= kg;
-            g[1] *= kg;
-            g[2] *= kg;
-        }
+        for (int a = 0; a < 3; a++) d[a] = a < L::DIM ? c.A * sa[a] + c.B * so[a] : R(0);
+        const R g[3] = {R(0), R(0), R(0)};
         const int p = pg_c;
         const unsigned site = unsigned(p * psz + Y[1] + X[1]);
         // collided populations (stored below)
         R out[Q];
-        const EqSite<R> es = collide<L, FORCE>(c, rho_dev, j, d, lap, g, fr[C0], out);
+        const EqSite<R> es =
+            collide<L, false>(c, rho_dev, j, d, lap, g, fr[C0], [&](int i, R v) { out[i] = v; });
         if (own && J.observe) {
             J.obs_rho[site] = double(rho_dev) + c.shift_sum;
-            R h = FORCE ? R(0.5) / es.rho : R(0);
-            J.obs_vel[site] = double(es.u[0] + h * g[0]);
-            J.obs_vel[J.obs_stride + site] = double(es.u[1] + h * g[1]);
-            J.obs_vel[2 * J.obs_stride + site] = double(L::DIM == 3 ? es.u[2] + h * g[2] : R(0));
+            J.obs_vel[site] = double(es.u[0]);
+            J.obs_vel[J.obs_stride + site] = double(es.u[1]);
+            J.obs_vel[2 * J.obs_stride + site] = double(L::DIM == 3 ? es.u[2] : R(0));
         }
         // Densities of the next plane: its ring slot (plane lc+H+1) is read by
-        // no thread in this iteration (the ring holds at least the H + 3
-        // planes lc - 1 .. lc + H + 1), so no barrier is needed before this
-        // store; the next iteration's first barrier
-        // publishes it.  The next gradient fill overwrites a plane read above
-        // only after that barrier.
-        if (more) store_rho(lc + H + 1, fr[CN], hr[HB]);
+        // no thread in this iteration (the ring holds the H + 3 planes
+        // lc - 1 .. lc + H + 1), so no barrier is needed before this store;
+        // the next iteration's barrier publishes it.
+        if (more) store_rho(lc + H + 1, fr[CN]);
         // Global stores after the wait for the prefetched loads: memory
         // counters retire in order, so a wait on a load issued before these
         // stores would also wait for their write acknowledgements.
@@ -489,7 +340,6 @@ __device__ __forceinline__ void step_tile(const Job<R> &J, const Coefs<R> &c)
         }
         advance(pg_c);
         advance(pg_f);
-        advance(pg_h);
     };
 
     // Full groups of H + 2 planes, every one of which prefetches: the loads
@@ -497,28 +347,37 @@ __device__ __forceinline__ void step_tile(const Job<R> &J, const Coefs<R> &c)
     // counting knows that the register ring is complete at the loop head (a
     // runtime prefetch condition made it wait for the fresh loads before the
     // collision).  The last group checks the condition at run time.
-    // (The halo double buffer alternates with the plane parity, which the
-    // ring phase keeps because the ring has H + 2 = 4 slots when HA = 2.)
-    static_assert(HA == 1 || (H + 2) % 2 == 0, "halo buffer parity follows the ring phase");
     using P0 = std::integral_constant<int, 0>;
     using P1 = std::integral_constant<int, 1>;
     using P2 = std::integral_constant<int, 2>;
-    using P3 = std::integral_constant<int, 3>;
     int k = 0;
-    for (; k + H + 1 + HA < npl; k += H + 2) {
+    for (; k + H + 2 < npl; k += H + 2) {
         iteration(k, P0{}, std::true_type{});
         iteration(k + 1, P1{}, std::true_type{});
         iteration(k + 2, P2{}, std::true_type{});
-        if constexpr (H == 2) iteration(k + 3, P3{}, std::true_type{});
     }
     for (; k < npl; k += H + 2) {
         iteration(k, P0{}, std::false_type{});
         if (k + 1 < npl) iteration(k + 1, P1{}, std::false_type{});
         if (k + 2 < npl) iteration(k + 2, P2{}, std::false_type{});
-        if constexpr (H == 2) {
-            if (k + 3 < npl) iteration(k + 3, P3{}, std::false_type{});
-        }
     }
+}
+
+} // namespace lbm
+
+#include "lbm_force.h"
+
+namespace lbm {
+
+// The step of one tile: the forcing scheme's march (lbm_force.h) or the
+// equilibrium scheme's.
+template <class L, int SCHEME, class S, class R, int TX, int TY>
+__device__ __forceinline__ void tile_step(const Job<R> &J, const Coefs<R> &c)
+{
+    if constexpr (SCHEME == SCHEME_FORCE)
+        force_tile<L, S, R, TX, TY>(J, c);
+    else
+        eq_tile<L, S, R, TX, TY>(J, c);
 }
 
 // One problem: workgroup b takes tile (b mod tiles_x, ...) of chunk b / tiles.
@@ -552,7 +411,7 @@ void step_kernel(StepArgs<R> A)
     J.write_pops = A.write_pops;
     J.observe = A.observe;
     if (J.npl <= 0) return;
-    step_tile<L, SCHEME, S, R, TX, TY>(J, A.c);
+    tile_step<L, SCHEME, S, R, TX, TY>(J, A.c);
 }
 
 // ---- many independent problems in one persistent launch --------------------
@@ -613,7 +472,7 @@ void batch_step_kernel(BatchArgs<R> B)
         J.npl = min(P.cp, P.np - J.p0);
         J.write_pops = B.write_pops;
         J.observe = B.observe;
-        step_tile<L, SCHEME, S, R, TX, TY>(J, B.coefs[k]);
+        tile_step<L, SCHEME, S, R, TX, TY>(J, B.coefs[k]);
         __syncthreads();  // the LDS rings are reused by the next item
     }
 }
