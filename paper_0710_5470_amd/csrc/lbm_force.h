@@ -28,6 +28,20 @@
 
 namespace lbm {
 
+#ifndef LBM_FORCE_DMA
+#define LBM_FORCE_DMA 1
+#endif
+
+// Workgroup barrier for LDS traffic only: waits for this wave's LDS
+// operations, not for its outstanding global loads.  (__syncthreads() is a
+// workgroup-scope fence, which must also wait for direct-to-LDS loads, i.e.
+// for the prefetch of the next planes.)  The memory clobber keeps the
+// compiler from moving memory accesses across it.
+__device__ __forceinline__ void lds_sync()
+{
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
 template <class L, class S, class R, int TX, int TY>
 __device__ __forceinline__ void force_tile(const Job<R> &J, const Coefs<R> &c)
 {
@@ -48,10 +62,18 @@ __device__ __forceinline__ void force_tile(const Job<R> &J, const Coefs<R> &c)
     constexpr int NBT = (NBORD + NT - 1) / NT;
     constexpr unsigned ES = sizeof(S);
     constexpr int RING = H + 2;                    // own-population planes in registers
+    // FP32: the density front's populations travel by direct-to-LDS loads
+    // into two staging planes, so plane lc + 4 is in flight while plane
+    // lc + 3 is taken into registers (see below); needs every halo site in
+    // one pass of the threads and the staging to fit the LDS.
+    constexpr int SPL = Q * NT;                    // floats per staging plane
+    constexpr bool DMA = LBM_FORCE_DMA && sizeof(S) == 4 && sizeof(R) == 4 &&
+                         (2 * SPL + NR * PL + NTC * GPL) * 4 <= 160 * 1024;
 
     __shared__ R rho_s[NR * PL];
     // T components: 3D xx, yy, zz, xy, xz, yz; 2D xx, xy (T_yy = -T_xx)
     __shared__ R t_s[NTC * GPL];
+    __shared__ float stage0[DMA ? SPL : 1], stage1[DMA ? SPL : 1];
 
     const S *src = static_cast<const S *>(J.src);
     S *dst = static_cast<S *>(J.dst);
@@ -131,11 +153,21 @@ __device__ __forceinline__ void force_tile(const Job<R> &J, const Coefs<R> &c)
     R dl[Q];         // own populations of the first planes (densities only)
     R hr[NHT][Q];    // halo populations loaded for densities
 
-    auto pull = [&](const int(&Xo)[3], const int(&Yo)[3], const int(&P)[3], R(&f)[Q]) {
+    // Byte offset past every buffer: loads from it return zero and stores to
+    // it are dropped by the buffer range check.  The DMA march issues its
+    // memory operations unconditionally, with this offset where a lane has
+    // nothing to load or store, so that every wave issues the same sequence
+    // and the compiler can count outstanding operations exactly (a
+    // conditional one makes it wait for all of them, prefetch included).
+    constexpr unsigned OOR = 0xFFFFFFFFu - (ES - 1);
+    // (offsets are or-ed with OOR rather than selected, which the compiler
+    // would turn into branches around duplicated loads)
+    auto pull = [&](const int(&Xo)[3], const int(&Yo)[3], const int(&P)[3], R(&f)[Q], bool valid = true) {
+        const unsigned oor = valid ? 0u : OOR;
 #pragma unroll
         for (int i = 0; i < Q; i++) {
             const unsigned e = unsigned(P[1 - op<L>(i)] + Yo[1 - oy<L>(i)] + Xo[1 - ox<L>(i)]);
-            f[i] = R(buf_load(rs, e * ES, unsigned(i * stride) * ES, S()));
+            f[i] = R(buf_load(rs, (e * ES) | oor, unsigned(i * stride) * ES, S()));
         }
     };
     // rho - sum_i s_i: moving populations first, the rest population last
@@ -155,12 +187,16 @@ __device__ __forceinline__ void force_tile(const Job<R> &J, const Coefs<R> &c)
         plane_offsets(pg, P);
         pull(X, Y, P, f);
     };
-    auto load_halo = [&](int pg) {
+    auto load_halo = [&](int pg, bool valid = true) {
         int P[3];
         plane_offsets(pg, P);
 #pragma unroll
-        for (int s = 0; s < NHT; s++)
-            if (hv[s]) pull(hX[s], hY[s], P, hr[s]);
+        for (int s = 0; s < NHT; s++) {
+            if constexpr (DMA)
+                pull(hX[s], hY[s], P, hr[s], valid && hv[s]);
+            else if (hv[s])
+                pull(hX[s], hY[s], P, hr[s]);
+        }
     };
     auto rho_at = [&](int lp, int lx, int ly) -> R & {
         return rho_s[(unsigned(lp) % NR) * PL + ly * TXH + lx];
@@ -171,6 +207,31 @@ __device__ __forceinline__ void force_tile(const Job<R> &J, const Coefs<R> &c)
 #pragma unroll
         for (int s = 0; s < NHT; s++)
             if (hv[s]) ring[hL[s]] = dens(hr[s]);
+    };
+
+    // Direct-to-LDS loads of a plane's own and halo populations into staging
+    // plane sb: wave w's lane l writes direction i of site w * 64 + l (own)
+    // or of halo site w * 64 + l, so each thread later reads back what its
+    // own wave wrote.
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    auto dma_front = [&](int pg, auto buf, bool valid) {
+        const unsigned oor = valid ? 0u : OOR;
+        int P[3];
+        plane_offsets(pg, P);
+#pragma unroll
+        for (int i = 0; i < Q; i++) {
+            const unsigned e = unsigned(P[1 - op<L>(i)] + Y[1 - oy<L>(i)] + X[1 - ox<L>(i)]);
+            float *const dst_l = (decltype(buf)::value ? stage1 : stage0) + i * NT + wave * 64;
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (__attribute__((address_space(3))) void *)dst_l, 4,
+                                                     (e * ES) | oor, unsigned(i * stride) * ES, 0, 0);
+        }
+    };
+    // take a staged plane's own populations into f and their density into
+    // the ring, with the halo densities from the halo loads in hr
+    auto take_front = [&](int lp, auto buf, R(&f)[Q]) {
+#pragma unroll
+        for (int i = 0; i < Q; i++) f[i] = decltype(buf)::value ? stage1[i * NT + tid] : stage0[i * NT + tid];
+        store_rho(lp, f);
     };
 
     // gradient of the density plane lp at density-ring site (rx, ry), summed
@@ -291,20 +352,24 @@ __device__ __forceinline__ void force_tile(const Job<R> &J, const Coefs<R> &c)
         store_rho(lp, f);
         __builtin_amdgcn_sched_barrier(0);
     }
-    __syncthreads();
+    // DMA: plane 2H + 1, taken in the first iteration (whose staging plane
+    // to take is stage1, see the iteration)
+    if constexpr (DMA) dma_front(gplane(2 * H + 1), std::true_type{}, npl > 1);
+    lds_sync();
     {
         R dd[3], ld, gx0[3] = {sum0<R>(), sum0<R>(), sum0<R>()};
         fill_t(H - 1, dd, ld);
-        __syncthreads();
+        lds_sync();
         add_t(gx0, gx0, gc);  // plane H - 1 reaches plane H through e_iz = -1
-        __syncthreads();
+        lds_sync();
         fill_t(H, dc, lapc);
-        __syncthreads();
+        lds_sync();
         add_t(gx0, gc, g1);
     }
 
-    // global planes of the collision and of the density front (lc + H + 1)
-    int pg_c = gplane(H), pg_f = gplane(2 * H + 1);
+    // global planes of the collision and of the density front (lc + H + 1;
+    // DMA: lc + H + 2 is the one issued)
+    int pg_c = gplane(H), pg_f = gplane(2 * H + 1), pg_f2 = gplane(2 * H + 2);
     auto advance = [&](int &pg) { pg = pg + 1 == np ? 0 : pg + 1; };
 
     auto iteration = [&](const int k, auto phase) {
@@ -314,16 +379,31 @@ __device__ __forceinline__ void force_tile(const Job<R> &J, const Coefs<R> &c)
         const bool more = k + 1 < npl;
         R(&fc)[Q] = fr[C0];
         R(&fn)[Q] = fr[CN];
+        // lc = H + phase (mod RING), RING even: the staging plane of plane
+        // lc + 4 (issued here) and of plane lc + 3 (taken here)
+        using SbIssue = std::integral_constant<bool, decltype(phase)::value % 2 != 0>;
+        using SbTake = std::integral_constant<bool, decltype(phase)::value % 2 == 0>;
         // Density front: plane lc + 3, in flight during this plane's work
         // (software pipelining: its memory latency overlaps the collision).
-        if (more) {
+        // DMA: only its halo populations here; the own ones were staged.
+        if constexpr (DMA)
+            load_halo(pg_f, more);
+        else if (more) {
             load_own(pg_f, fn);
             load_halo(pg_f);
         }
-        __syncthreads();  // densities up to plane lc + 2 in LDS; T plane free
+        lds_sync();  // densities up to plane lc + 2 in LDS; T plane free
+        // DMA: own populations of plane lc + 4 into the staging plane taken
+        // in the previous iteration (every thread is past its reads), taken
+        // in the next iteration: in flight for two planes of work
+        if constexpr (DMA) dma_front(pg_f2, SbIssue{}, k + 2 < npl);
         fill_t(lc + 1, dn, lapn);
-        __syncthreads();  // T of plane lc + 1 in LDS
+        lds_sync();  // T of plane lc + 1 in LDS
         add_t(gc, g1, g2);
+        // DMA: plane lc + 3 into the ring now, before this plane's stores,
+        // so that waiting for its staged loads leaves plane lc + 4's in flight
+        // (memory counters retire in order)
+        if (DMA && more) take_front(lc + H + 1, SbTake{}, fn);
 
         const R rho_dev = rho_at(lc, tx + H, ty + HY);
         R j[3] = {sum0<R>(), sum0<R>(), DIM == 3 ? sum0<R>() : R(0)};
@@ -339,8 +419,12 @@ __device__ __forceinline__ void force_tile(const Job<R> &J, const Coefs<R> &c)
 
         const unsigned site = unsigned(pg_c * psz + Y[1] + X[1]);
         const bool st = own && J.write_pops;
+        const unsigned soor = st ? 0u : OOR;
         const EqSite<R> es = collide<L, true>(c, rho_dev, j, dc, lapc, g, fc, [&](int i, R v) {
-            if (st) buf_store(rd, site * ES, unsigned(i * stride) * ES, S(v));
+            if constexpr (DMA)
+                buf_store(rd, (site * ES) | soor, unsigned(i * stride) * ES, S(v));
+            else if (st)
+                buf_store(rd, site * ES, unsigned(i * stride) * ES, S(v));
         });
         if (own && J.observe) {
             J.obs_rho[site] = double(rho_dev) + c.shift_sum;
@@ -353,7 +437,7 @@ __device__ __forceinline__ void force_tile(const Job<R> &J, const Coefs<R> &c)
         // thread reads in this iteration; the next iteration's first barrier
         // publishes them.  The population stores above went out after the
         // front's loads, so waiting for those loads does not wait for them.
-        if (more) store_rho(lc + H + 1, fn);
+        if (!DMA && more) store_rho(lc + H + 1, fn);
 #pragma unroll
         for (int a = 0; a < 3; a++) {
             gc[a] = g1[a];
@@ -364,6 +448,7 @@ __device__ __forceinline__ void force_tile(const Job<R> &J, const Coefs<R> &c)
         lapc = lapn;
         advance(pg_c);
         advance(pg_f);
+        advance(pg_f2);
     };
 
     using P0 = std::integral_constant<int, 0>;
