@@ -67,8 +67,8 @@ __device__ __forceinline__ void force_tile(const Job<R> &J, const Coefs<R> &c)
     // lc + 3 is taken into registers (see below); needs every halo site in
     // one pass of the threads and the staging to fit the LDS.
     constexpr int SPL = Q * NT;                    // floats per staging plane
-    constexpr bool DMA = LBM_FORCE_DMA && sizeof(S) == 4 && sizeof(R) == 4 &&
-                         (2 * SPL + NR * PL + NTC * GPL) * 4 <= 160 * 1024;
+    constexpr bool DMA = LBM_FORCE_DMA && sizeof(S) == 4 &&
+                         2 * SPL * 4 + (NR * PL + NTC * GPL) * sizeof(R) <= 160 * 1024;
 
     __shared__ R rho_s[NR * PL];
     // T components: 3D xx, yy, zz, xy, xz, yz; 2D xx, xy (T_yy = -T_xx)
@@ -149,9 +149,11 @@ __device__ __forceinline__ void force_tile(const Job<R> &J, const Coefs<R> &c)
         bL[s] = bv[s] ? ly * TXG + lx : 0;
     }
 
-    R fr[RING][Q];   // own populations: plane lc + k in fr[(phase + k) % RING]
-    R dl[Q];         // own populations of the first planes (densities only)
-    R hr[NHT][Q];    // halo populations loaded for densities
+    // Populations are held as stored (S) and widened where used, so FP32
+    // storage with FP64 arithmetic keeps its register ring in FP32.
+    S fr[RING][Q];   // own populations: plane lc + k in fr[(phase + k) % RING]
+    S dl[Q];         // own populations of the first planes (densities only)
+    S hr[NHT][Q];    // halo populations loaded for densities
 
     // Byte offset past every buffer: loads from it return zero and stores to
     // it are dropped by the buffer range check.  The DMA march issues its
@@ -162,27 +164,27 @@ __device__ __forceinline__ void force_tile(const Job<R> &J, const Coefs<R> &c)
     constexpr unsigned OOR = 0xFFFFFFFFu - (ES - 1);
     // (offsets are or-ed with OOR rather than selected, which the compiler
     // would turn into branches around duplicated loads)
-    auto pull = [&](const int(&Xo)[3], const int(&Yo)[3], const int(&P)[3], R(&f)[Q], bool valid = true) {
+    auto pull = [&](const int(&Xo)[3], const int(&Yo)[3], const int(&P)[3], S(&f)[Q], bool valid = true) {
         const unsigned oor = valid ? 0u : OOR;
 #pragma unroll
         for (int i = 0; i < Q; i++) {
             const unsigned e = unsigned(P[1 - op<L>(i)] + Yo[1 - oy<L>(i)] + Xo[1 - ox<L>(i)]);
-            f[i] = R(buf_load(rs, (e * ES) | oor, unsigned(i * stride) * ES, S()));
+            f[i] = buf_load(rs, (e * ES) | oor, unsigned(i * stride) * ES, S());
         }
     };
     // rho - sum_i s_i: moving populations first, the rest population last
-    auto dens = [&](const R(&f)[Q]) -> R {
+    auto dens = [&](const S(&f)[Q]) -> R {
         R s = sum0<R>();
 #pragma unroll
-        for (int i = 1; i < Q; i++) s += f[i];
-        return s + f[0];
+        for (int i = 1; i < Q; i++) s += R(f[i]);
+        return s + R(f[0]);
     };
     auto plane_offsets = [&](int p, int(&P)[3]) {
         P[0] = wrap1(p - 1, np) * psz;
         P[1] = p * psz;
         P[2] = wrap1(p + 1, np) * psz;
     };
-    auto load_own = [&](int pg, R(&f)[Q]) {
+    auto load_own = [&](int pg, S(&f)[Q]) {
         int P[3];
         plane_offsets(pg, P);
         pull(X, Y, P, f);
@@ -201,7 +203,7 @@ __device__ __forceinline__ void force_tile(const Job<R> &J, const Coefs<R> &c)
     auto rho_at = [&](int lp, int lx, int ly) -> R & {
         return rho_s[(unsigned(lp) % NR) * PL + ly * TXH + lx];
     };
-    auto store_rho = [&](int lp, const R(&f)[Q]) {
+    auto store_rho = [&](int lp, const S(&f)[Q]) {
         R *ring = rho_s + (unsigned(lp) % NR) * PL;
         ring[(ty + HY) * TXH + tx + H] = dens(f);
 #pragma unroll
@@ -228,7 +230,7 @@ __device__ __forceinline__ void force_tile(const Job<R> &J, const Coefs<R> &c)
     };
     // take a staged plane's own populations into f and their density into
     // the ring, with the halo densities from the halo loads in hr
-    auto take_front = [&](int lp, auto buf, R(&f)[Q]) {
+    auto take_front = [&](int lp, auto buf, S(&f)[Q]) {
 #pragma unroll
         for (int i = 0; i < Q; i++) f[i] = decltype(buf)::value ? stage1[i * NT + tid] : stage0[i * NT + tid];
         store_rho(lp, f);
@@ -346,7 +348,7 @@ __device__ __forceinline__ void force_tile(const Job<R> &J, const Coefs<R> &c)
     for (int a = 0; a < 3; a++) gc[a] = g1[a] = g2[a] = sum0<R>();
 #pragma unroll
     for (int lp = 0; lp <= 2 * H; lp++) {
-        R(&f)[Q] = lp >= H ? fr[(lp - H) % RING] : dl;
+        S(&f)[Q] = lp >= H ? fr[(lp - H) % RING] : dl;
         load_own(gplane(lp), f);
         load_halo(gplane(lp));
         store_rho(lp, f);
@@ -377,8 +379,8 @@ __device__ __forceinline__ void force_tile(const Job<R> &J, const Coefs<R> &c)
         constexpr int CN = (decltype(phase)::value + H + 1) % RING;  // plane lc + H + 1
         const int lc = H + k;
         const bool more = k + 1 < npl;
-        R(&fc)[Q] = fr[C0];
-        R(&fn)[Q] = fr[CN];
+        S(&fc)[Q] = fr[C0];
+        S(&fn)[Q] = fr[CN];
         // lc = H + phase (mod RING), RING even: the staging plane of plane
         // lc + 4 (issued here) and of plane lc + 3 (taken here)
         using SbIssue = std::integral_constant<bool, decltype(phase)::value % 2 != 0>;
@@ -409,9 +411,9 @@ __device__ __forceinline__ void force_tile(const Job<R> &J, const Coefs<R> &c)
         R j[3] = {sum0<R>(), sum0<R>(), DIM == 3 ? sum0<R>() : R(0)};
 #pragma unroll
         for (int i = 1; i < Q; i++) {
-            if (L::ex[i]) j[0] += R(L::ex[i]) * fc[i];
-            if (L::ey[i]) j[1] += R(L::ey[i]) * fc[i];
-            if (L::ez[i]) j[2] += R(L::ez[i]) * fc[i];
+            if (L::ex[i]) j[0] += R(L::ex[i]) * R(fc[i]);
+            if (L::ey[i]) j[1] += R(L::ey[i]) * R(fc[i]);
+            if (L::ez[i]) j[2] += R(L::ez[i]) * R(fc[i]);
         }
         R g[3];
 #pragma unroll
@@ -420,7 +422,10 @@ __device__ __forceinline__ void force_tile(const Job<R> &J, const Coefs<R> &c)
         const unsigned site = unsigned(pg_c * psz + Y[1] + X[1]);
         const bool st = own && J.write_pops;
         const unsigned soor = st ? 0u : OOR;
-        const EqSite<R> es = collide<L, true>(c, rho_dev, j, dc, lapc, g, fc, [&](int i, R v) {
+        R fin[Q];
+#pragma unroll
+        for (int i = 0; i < Q; i++) fin[i] = R(fc[i]);
+        const EqSite<R> es = collide<L, true>(c, rho_dev, j, dc, lapc, g, fin, [&](int i, R v) {
             if constexpr (DMA)
                 buf_store(rd, (site * ES) | soor, unsigned(i * stride) * ES, S(v));
             else if (st)
