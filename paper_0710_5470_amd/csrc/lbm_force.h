@@ -32,16 +32,6 @@ namespace lbm {
 #define LBM_FORCE_DMA 1
 #endif
 
-// Workgroup barrier for LDS traffic only: waits for this wave's LDS
-// operations, not for its outstanding global loads.  (__syncthreads() is a
-// workgroup-scope fence, which must also wait for direct-to-LDS loads, i.e.
-// for the prefetch of the next planes.)  The memory clobber keeps the
-// compiler from moving memory accesses across it.
-__device__ __forceinline__ void lds_sync()
-{
-    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
-}
-
 template <class L, class S, class R, int TX, int TY>
 __device__ __forceinline__ void force_tile(const Job<R> &J, const Coefs<R> &c)
 {

@@ -110,6 +110,16 @@ template <class R> struct Job {
     int write_pops, observe;
 };
 
+// Workgroup barrier for LDS traffic only: waits for this wave's LDS
+// operations, not for its outstanding global loads.  (__syncthreads() is a
+// workgroup-scope fence, which must also wait for direct-to-LDS loads, i.e.
+// for the prefetch of the next planes.)  The memory clobber keeps the
+// compiler from moving memory accesses across it.
+__device__ __forceinline__ void lds_sync()
+{
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
 // The equilibrium scheme (Eq. (equilibrium)): gradients and Laplacian of
 // the density are needed one site away, so the ring holds the tile plus a
 // 1-site halo and the own populations stay in registers for H + 1 = 2
@@ -363,19 +373,264 @@ __device__ __forceinline__ void eq_tile(const Job<R> &J, const Coefs<R> &c)
     }
 }
 
+// The equilibrium march for FP32 storage, with the density front's own
+// populations staged by direct-to-LDS loads (buffer_load ... lds) into two
+// staging planes, as in the forcing march: plane lc + 3 is issued in the
+// iteration that collides plane lc and taken into the register ring in the
+// next one, after its collision and before its stores, so the staged loads
+// have about two planes of work to arrive and hold no registers meanwhile.
+// Memory operations are issued unconditionally (out-of-range offsets where a
+// lane has nothing to do), so that the compiler counts the outstanding ones
+// exactly and leaves the newest staged plane in flight.
+template <class L, class S, class R, int TX, int TY>
+__device__ __forceinline__ void eq_tile_dma(const Job<R> &J, const Coefs<R> &c)
+{
+    constexpr int Q = L::Q;
+    constexpr int H = 1;
+    constexpr int HY = L::DIM == 3 ? H : 0;
+    constexpr int TXH = TX + 2 * H, TYH = TY + 2 * HY;
+    constexpr int PL = TXH * TYH;
+    constexpr int NR = 4;                       // density planes lc - 1 .. lc + 2
+    constexpr int NT = TX * TY;
+    constexpr int NHALO = 2 * HY * TXH + 2 * H * TY;
+    constexpr int NHT = (NHALO + NT - 1) / NT;
+    constexpr unsigned ES = sizeof(S);
+    constexpr int RING = 2;                     // planes lc, lc + 1 (lc + 2 taken into lc's slot)
+    constexpr int SPL = Q * NT;                 // floats per staging plane
+    constexpr unsigned OOR = 0xFFFFFFFFu - (ES - 1);
+
+    __shared__ R rho_s[NR * PL];
+    __shared__ float stage0[SPL], stage1[SPL];
+
+    const S *src = static_cast<const S *>(J.src);
+    S *dst = static_cast<S *>(J.dst);
+    const long long stride = J.stride;
+    const int nx = J.nx, ny = J.ny, np = J.np;
+    const int psz = nx * ny;
+    const int x0 = J.x0, y0 = J.y0, p0 = J.p0, npl = J.npl;
+    const __amdgpu_buffer_rsrc_t rs = pop_rsrc(src, J.bytes);
+    const __amdgpu_buffer_rsrc_t rd = pop_rsrc(dst, J.bytes);
+
+    const int tid = threadIdx.x;
+    const int tx = tid % TX, ty = tid / TX;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    int X[3], Y[3];
+    const int gx = wrapg(x0 + tx, nx);
+    const int gy = L::DIM == 3 ? wrapg(y0 + ty, ny) : 0;
+    X[0] = wrap1(gx - 1, nx); X[1] = gx; X[2] = wrap1(gx + 1, nx);
+    if (L::DIM == 3) {
+        Y[0] = wrap1(gy - 1, ny) * nx; Y[1] = gy * nx; Y[2] = wrap1(gy + 1, ny) * nx;
+    } else {
+        Y[0] = Y[1] = Y[2] = 0;
+    }
+    const bool own = (x0 + tx < nx) && (L::DIM == 2 || y0 + ty < ny);
+
+    int hX[NHT][3], hY[NHT][3], hL[NHT];
+    bool hv[NHT];
+#pragma unroll
+    for (int s = 0; s < NHT; s++) {
+        const int k = tid + s * NT;
+        hv[s] = k < NHALO;
+        int lx = 0, ly = 0;
+        if (k < HY * TXH) {
+            ly = k / TXH;
+            lx = k % TXH;
+        } else if (k < 2 * HY * TXH) {
+            const int kk = k - HY * TXH;
+            ly = TY + HY + kk / TXH;
+            lx = kk % TXH;
+        } else {
+            const int kk = k - 2 * HY * TXH;
+            const int cc = kk % (2 * H);
+            ly = HY + kk / (2 * H);
+            lx = cc < H ? cc : TX + cc;
+        }
+        if (!hv[s]) lx = ly = 0;
+        hL[s] = ly * TXH + lx;
+        const int hx = wrapg(x0 - H + lx, nx);
+        const int hy = L::DIM == 3 ? wrapg(y0 - HY + ly, ny) : 0;
+        hX[s][0] = wrap1(hx - 1, nx); hX[s][1] = hx; hX[s][2] = wrap1(hx + 1, nx);
+        if (L::DIM == 3) {
+            hY[s][0] = wrap1(hy - 1, ny) * nx; hY[s][1] = hy * nx; hY[s][2] = wrap1(hy + 1, ny) * nx;
+        } else {
+            hY[s][0] = hY[s][1] = hY[s][2] = 0;
+        }
+    }
+
+    S fr[RING][Q];   // own populations: plane lc + k in fr[(phase + k) % RING]
+    S dl[Q];         // own populations of the first plane (density only)
+    S hr[NHT][Q];    // halo populations loaded for densities
+
+    auto pull = [&](const int(&Xo)[3], const int(&Yo)[3], const int(&P)[3], S(&f)[Q], bool valid) {
+        const unsigned oor = valid ? 0u : OOR;
+#pragma unroll
+        for (int i = 0; i < Q; i++) {
+            const unsigned e = unsigned(P[1 - op<L>(i)] + Yo[1 - oy<L>(i)] + Xo[1 - ox<L>(i)]);
+            f[i] = buf_load(rs, (e * ES) | oor, unsigned(i * stride) * ES, S());
+        }
+    };
+    auto dens = [&](const S(&f)[Q]) -> R {
+        R s = sum0<R>();
+#pragma unroll
+        for (int i = 1; i < Q; i++) s += R(f[i]);
+        return s + R(f[0]);
+    };
+    auto plane_offsets = [&](int p, int(&P)[3]) {
+        P[0] = wrap1(p - 1, np) * psz;
+        P[1] = p * psz;
+        P[2] = wrap1(p + 1, np) * psz;
+    };
+    auto rho_at = [&](int lp, int lx, int ly) -> R & {
+        return rho_s[(unsigned(lp) % NR) * PL + ly * TXH + lx];
+    };
+    auto load_own = [&](int pg, S(&f)[Q]) {
+        int P[3];
+        plane_offsets(pg, P);
+        pull(X, Y, P, f, true);
+    };
+    auto load_halo = [&](int pg, bool valid) {
+        int P[3];
+        plane_offsets(pg, P);
+#pragma unroll
+        for (int s = 0; s < NHT; s++) pull(hX[s], hY[s], P, hr[s], valid && hv[s]);
+    };
+    auto store_rho = [&](int lp, const S(&f)[Q]) {
+        R *ring = rho_s + (unsigned(lp) % NR) * PL;
+        ring[(ty + HY) * TXH + tx + H] = dens(f);
+#pragma unroll
+        for (int s = 0; s < NHT; s++)
+            if (hv[s]) ring[hL[s]] = dens(hr[s]);
+    };
+    auto dma_front = [&](int pg, auto buf, bool valid) {
+        const unsigned oor = valid ? 0u : OOR;
+        int P[3];
+        plane_offsets(pg, P);
+#pragma unroll
+        for (int i = 0; i < Q; i++) {
+            const unsigned e = unsigned(P[1 - op<L>(i)] + Y[1 - oy<L>(i)] + X[1 - ox<L>(i)]);
+            float *const dst_l = (decltype(buf)::value ? stage1 : stage0) + i * NT + wave * 64;
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (__attribute__((address_space(3))) void *)dst_l, 4,
+                                                     (e * ES) | oor, unsigned(i * stride) * ES, 0, 0);
+        }
+    };
+    auto take_front = [&](int lp, auto buf, S(&f)[Q]) {
+#pragma unroll
+        for (int i = 0; i < Q; i++) f[i] = decltype(buf)::value ? stage1[i * NT + tid] : stage0[i * NT + tid];
+        store_rho(lp, f);
+    };
+
+    auto gplane = [&](int lp) { return __builtin_amdgcn_readfirstlane(wrapg(p0 - H + lp, np)); };
+    // prologue: densities of local planes 0 .. 2H (global p0 - 1 .. p0 + 1;
+    // the own populations of planes H, H + 1 stay in the ring), and the
+    // staged plane 2H + 1, taken in the first iteration (from stage1)
+    load_own(gplane(0), dl);
+    load_halo(gplane(0), true);
+    store_rho(0, dl);
+    __builtin_amdgcn_sched_barrier(0);
+    load_own(gplane(1), fr[0]);
+    load_halo(gplane(1), true);
+    store_rho(1, fr[0]);
+    __builtin_amdgcn_sched_barrier(0);
+    load_own(gplane(2), fr[1]);
+    load_halo(gplane(2), true);
+    store_rho(2, fr[1]);
+    dma_front(gplane(3), std::true_type{}, npl > 1);
+
+    // global planes of the collision, of the halo front taken this
+    // iteration (lc + 2) and of the staged plane issued (lc + 3)
+    int pg_c = gplane(H), pg_f = gplane(2 * H + 1), pg_f2 = gplane(2 * H + 2);
+    auto advance = [&](int &pg) { pg = pg + 1 == np ? 0 : pg + 1; };
+
+    auto iteration = [&](const int k, auto phase) {
+        constexpr int C0 = decltype(phase)::value % RING;  // plane lc (lc + 2 after the take)
+        using SbIssue = std::integral_constant<bool, decltype(phase)::value % 2 != 0>;
+        using SbTake = std::integral_constant<bool, decltype(phase)::value % 2 == 0>;
+        const int lc = H + k;
+        const bool more = k + 1 < npl;
+        // halo populations of plane lc + 2, consumed after the collision
+        load_halo(pg_f, more);
+        lds_sync();  // densities up to plane lc + 1 in LDS
+        // own populations of plane lc + 3, taken in the next iteration
+        dma_front(pg_f2, SbIssue{}, k + 2 < npl);
+        const int lx = tx + H, ly = ty + HY;
+        const R rho_dev = rho_at(lc, lx, ly);
+        S(&fc)[Q] = fr[C0];
+        R j[3] = {sum0<R>(), sum0<R>(), L::DIM == 3 ? sum0<R>() : R(0)};
+#pragma unroll
+        for (int i = 1; i < Q; i++) {
+            if (L::ex[i]) j[0] += R(L::ex[i]) * R(fc[i]);
+            if (L::ey[i]) j[1] += R(L::ey[i]) * R(fc[i]);
+            if (L::ez[i]) j[2] += R(L::ez[i]) * R(fc[i]);
+        }
+        R sa[3] = {sum0<R>(), sum0<R>(), sum0<R>()}, so[3] = {sum0<R>(), sum0<R>(), sum0<R>()};
+        R lap = sum0<R>();
+#pragma unroll
+        for (int i = 1; i < Q; i++) {
+            const R r = rho_at(lc + op<L>(i), lx + ox<L>(i), ly + oy<L>(i));
+            R *acc = nnz<L>(i) == 1 ? sa : so;
+            if (L::ex[i]) acc[0] += R(L::ex[i]) * r;
+            if (L::ey[i]) acc[1] += R(L::ey[i]) * r;
+            if (L::ez[i]) acc[2] += R(L::ez[i]) * r;
+            lap += coef_lap<L>(c, i) * (r - rho_dev);
+        }
+        R d[3];
+#pragma unroll
+        for (int a = 0; a < 3; a++) d[a] = a < L::DIM ? c.A * sa[a] + c.B * so[a] : R(0);
+        const R g[3] = {R(0), R(0), R(0)};
+        const unsigned site = unsigned(pg_c * psz + Y[1] + X[1]);
+        R fin[Q], out[Q];
+#pragma unroll
+        for (int i = 0; i < Q; i++) fin[i] = R(fc[i]);
+        const EqSite<R> es = collide<L, false>(c, rho_dev, j, d, lap, g, fin, [&](int i, R v) { out[i] = v; });
+        if (own && J.observe) {
+            J.obs_rho[site] = double(rho_dev) + c.shift_sum;
+            J.obs_vel[site] = double(es.u[0]);
+            J.obs_vel[J.obs_stride + site] = double(es.u[1]);
+            J.obs_vel[2 * J.obs_stride + site] = double(L::DIM == 3 ? es.u[2] : R(0));
+        }
+        // plane lc + 2 into this plane's ring slot (its ring-of-densities slot
+        // held plane lc - 2, read by no thread since the barrier above),
+        // before the stores, so that waiting for its staged loads leaves
+        // plane lc + 3's in flight
+        if (more) take_front(lc + H + 1, SbTake{}, fc);
+        const unsigned soor = (own && J.write_pops) ? 0u : OOR;
+#pragma unroll
+        for (int i = 0; i < Q; i++) buf_store(rd, (site * ES) | soor, unsigned(i * stride) * ES, S(out[i]));
+        advance(pg_c);
+        advance(pg_f);
+        advance(pg_f2);
+    };
+
+    using P0 = std::integral_constant<int, 0>;
+    using P1 = std::integral_constant<int, 1>;
+    for (int k = 0; k < npl; k += RING) {
+        iteration(k, P0{});
+        if (k + 1 < npl) iteration(k + 1, P1{});
+    }
+}
+
 } // namespace lbm
 
 #include "lbm_force.h"
 
 namespace lbm {
 
+#ifndef LBM_EQ_DMA
+#define LBM_EQ_DMA 1
+#endif
+
 // The step of one tile: the forcing scheme's march (lbm_force.h) or the
-// equilibrium scheme's.
+// equilibrium scheme's (FP32 storage: with staged loads).
 template <class L, int SCHEME, class S, class R, int TX, int TY>
 __device__ __forceinline__ void tile_step(const Job<R> &J, const Coefs<R> &c)
 {
+    constexpr int NT = TX * TY, Q = L::Q, PLE = (TX + 2) * (TY + (L::DIM == 3 ? 2 : 0));
+    constexpr bool EQ_DMA =
+        LBM_EQ_DMA && sizeof(S) == 4 && (2 * Q * NT * 4 + 4 * PLE * int(sizeof(R))) <= 160 * 1024;
     if constexpr (SCHEME == SCHEME_FORCE)
         force_tile<L, S, R, TX, TY>(J, c);
+    else if constexpr (EQ_DMA)
+        eq_tile_dma<L, S, R, TX, TY>(J, c);
     else
         eq_tile<L, S, R, TX, TY>(J, c);
 }
