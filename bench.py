@@ -37,7 +37,8 @@ WORKLOADS = {
     "d2q9_1024_fp64_eq": (9, 0, 0, 0, (1024, 1024), 0.56, 0.01, 1.0, 28.0, 0.0),
     "d2q9_1024_fp32_force": (9, 1, 1, 0, (1024, 1024), 0.56, 0.01, 1.0, 28.0, 0.0),
 }
-KERNEL_SOURCES = ["paper_0710_5470_amd/csrc/lbm_step.h", "paper_0710_5470_amd/csrc/lbm_lattice.h"]
+KERNEL_SOURCES = ["paper_0710_5470_amd/csrc/lbm_step.h", "paper_0710_5470_amd/csrc/lbm_force.h",
+                  "paper_0710_5470_amd/csrc/lbm_lattice.h"]
 
 
 def make_workload(wl):
@@ -88,6 +89,43 @@ def measured_traffic(workload):
     return d.get("hbm_bytes_per_launch")
 
 
+def cpu_model():
+    """The host CPU's model name as /proc/cpuinfo reports it."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def copy_ceiling(nbytes, reps=20):
+    """GB/s (bytes read + bytes written) of the library's streaming copy of
+    nbytes, timed with HIP events on the current stream: the rate the step
+    kernel's algorithmic traffic (read and write every population once) is
+    compared with."""
+    import torch
+    from paper_0710_5470_amd import lbm
+    n = (nbytes + 15) // 16 * 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    lbm.lbm_stream_copy(a, b, n * 4)
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(reps):
+        lbm.lbm_stream_copy(a, b, n * 4)
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    ok = bool(torch.equal(a[:1024], b[:1024]))
+    del a, b
+    return 2 * n * 4 / (ms * 1e-3) / 1e9, ms, ok
+
+
 def cpu_baseline(wl):
     """Time the FP64 CPU oracle on a bounded sample of the same workload: a
     256 x 256 x 48 periodic slab (D3Q19) or a 1024 x 1024 box (D2Q9) with
@@ -106,33 +144,29 @@ def cpu_baseline(wl):
     p = oracle.params(q=q, scheme=scheme, shape=sample, T=T, kappa=kappa, tau=tau)
     f = oracle.init(p, rho)
     steps = 36 if q == 19 else 150
+    cores = oracle.max_threads()
     t0 = time.perf_counter()
     f = oracle.run(p, f, steps)
     dt = time.perf_counter() - t0
     sites = int(np.prod(sample))
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    # one thread, one step of the same sample
+    oracle.set_threads(1)
+    t1 = time.perf_counter()
+    oracle.run(p, f, 1)
+    dt1 = time.perf_counter() - t1
+    oracle.set_threads(cores)
     return {"value": sites * steps / dt / 1e6, "unit": "MLUPS", "cores": cores, "kind": "oracle",
             "sample": "%s periodic lattice, same physics, %d steps, FP64 C oracle (%.2f s)"
-                      % ("x".join(map(str, sample)), steps, dt)}
+                      % ("x".join(map(str, sample)), steps, dt),
+            "cpu_model": cpu_model(), "single_thread_mlups": sites / dt1 / 1e6}
 
 
 def copy_calibration(nbytes, reps):
-    """A plain device-to-device copy of nbytes (read nbytes, write nbytes),
+    """The library's streaming copy of nbytes (read nbytes, write nbytes),
     repeated; its FETCH_SIZE / WRITE_SIZE counters scale the LBM kernel's."""
-    import torch
-    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
-    b = torch.empty_like(a)
-    b.copy_(a)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
-        b.copy_(a)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / reps
-    print(json.dumps({"copy_bytes": a.numel() * 4, "reps": reps, "ms": ms,
-                      "GBps_read_plus_write": 2 * a.numel() * 4 / (ms * 1e-3) / 1e9}), flush=True)
+    gbs, ms, ok = copy_ceiling(nbytes, reps)
+    print(json.dumps({"copy_bytes": (nbytes + 15) // 16 * 16, "reps": reps, "ms": ms,
+                      "GBps_read_plus_write": gbs, "ok": ok}), flush=True)
 
 
 def main():
@@ -225,6 +259,14 @@ def main():
     }
     sim.close()
     del sim
+    # measured ceiling: the streaming copy of the same bytes per launch
+    # (bytes_site / 2 read and as many written per site)
+    cgbs, cms, cok = copy_ceiling(bytes_site * n // 2)
+    out["roofline"]["copy_ceiling_gbs"] = round(cgbs, 1)
+    out["roofline"]["frac_of_copy"] = round(achieved / cgbs, 4)
+    out["roofline"]["copy_ms"] = round(cms, 5)
+    if not cok:
+        raise RuntimeError("stream copy check failed")
     if not args.no_batched:
         # second half of the metric: 512 held-out 128^2 drops (FP64 storage,
         # residual 1e-10), cold start versus the shipped warm-start network

@@ -346,6 +346,16 @@ int lbm_warm_project(int nprob, int side, int cpad, const float *dev_pred, const
                      double s_u, int with_velocity, int symmetrize, double rho_lo, double rho_hi, double *dev_rho,
                      double *dev_u, void *stream);
 
+/* ---- measurement --------------------------------------------------------
+ *
+ * Copy `bytes` (a multiple of 16, below 2^43; both pointers 16-byte aligned) from
+ * dev_src to dev_dst with a streaming kernel (16-byte loads, non-temporal
+ * 16-byte stores).  Not part of the method: it measures the HBM rate one
+ * read plus one write of every byte can reach, the ceiling the step
+ * kernels' algorithmic traffic is compared with.  Only enqueues work;
+ * LBM_E_INVAL for a bad size or alignment. */
+int lbm_stream_copy(const void *dev_src, void *dev_dst, size_t bytes, void *stream);
+
 /* Human-readable name of a status code. */
 const char *lbm_strerror(int code);
 

@@ -52,6 +52,8 @@ def lib():
         L.orc_p0.restype = ctypes.c_double
         L.orc_cs2.argtypes = [ctypes.c_double] * 4
         L.orc_cs2.restype = ctypes.c_double
+        L.orc_set_threads.argtypes = [ctypes.c_int]
+        L.orc_max_threads.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -189,3 +191,12 @@ def p0(a, b, T, rho):
 
 def cs2(a, b, T, rho):
     return lib().orc_cs2(a, b, T, rho)
+
+
+def set_threads(n):
+    """Threads of the oracle's OpenMP loops (no effect on results)."""
+    lib().orc_set_threads(int(n))
+
+
+def max_threads():
+    return int(lib().orc_max_threads())

@@ -42,6 +42,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 typedef struct {
     int q;          /* 9 = D2Q9, 19 = D3Q19 */
@@ -675,4 +678,24 @@ void orc_totals(const orc_params *p, const double *f, double *mass, double *mom)
     mom[0] = mx;
     mom[1] = my;
     mom[2] = mz;
+}
+
+/* Thread count of the OpenMP loops (results do not depend on it: every
+ * site is computed independently and the totals are serial). */
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
+int orc_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }

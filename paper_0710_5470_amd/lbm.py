@@ -87,6 +87,7 @@ _sig = {
     "lbm_batch_set_launch": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int]),
     "lbm_batch_get_launch": (ctypes.c_int, [_vp, _ip, _ip, _ip]),
     "lbm_batch_destroy": (ctypes.c_int, [_vp]),
+    "lbm_stream_copy": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t, _vp]),
 }
 
 
@@ -251,6 +252,11 @@ def lbm_coexistence(a, b, T):
     _check(_L.lbm_coexistence(float(a), float(b), float(T), ctypes.byref(g), ctypes.byref(l)),
            "lbm_coexistence")
     return g.value, l.value
+
+
+def lbm_stream_copy(src, dst, nbytes, stream=None):
+    """Streaming device copy of nbytes (measurement of the HBM ceiling)."""
+    _check(_L.lbm_stream_copy(_ptr(src), _ptr(dst), int(nbytes), _stream(stream)), "lbm_stream_copy")
 
 
 def _params_array(plist):
