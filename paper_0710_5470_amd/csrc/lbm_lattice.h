@@ -312,7 +312,9 @@ __device__ __forceinline__ EqSite<R> collide(const Coefs<R> &c, R rho_dev, const
         const R eu = edot<L>(i, s.u);
         R E = (R(1.5) * om * w) * exe<L>(s, i, eu, edot<L>(i, d)) + K[axis ? 0 : 1];
         if (!FORCE) E += om * m_terms<L>(c, s, i);
-        R D = (axis ? c.ow_ax : c.ow_off) * edot<L>(i, j);
+        // FP32: omega w from the exact pairs (the first-moment identity then
+        // holds exactly in FP32); FP64: formed here (one register pair fewer)
+        R D = (F32 ? (axis ? c.ow_ax : c.ow_off) : om * w) * edot<L>(i, j);
         if (FORCE) {
             const R eg = edot<L>(i, g);
             E += (R(3) * w * eu) * eg;
