@@ -11,8 +11,10 @@ Prints ONE JSON line: MLUPS (whole job), the dominant kernel's roofline
 (algorithmic bytes = 19 populations read + written = 152 B per site for
 FP32, over the average launch time from HIP events on the launch stream),
 the batched time-to-steady of 512 held-out 128^2 drops from the cold start
-and from the shipped warm-start network (--no-batched skips it), and the
-FP64 CPU oracle timed on the host cores on a bounded sample.
+and from the shipped warm-start network (--no-batched skips it), the cold
+time-to-steady of 512 drops on uneven lattices (side 32..256) in FP32 and
+FP64 storage (--no-uneven skips it), and the FP64 CPU oracle timed on the
+host cores on a bounded sample.
 """
 import argparse
 import hashlib
@@ -37,6 +39,9 @@ WORKLOADS = {
     "d2q9_1024_fp64_eq": (9, 0, 0, 0, (1024, 1024), 0.56, 0.01, 1.0, 28.0, 0.0),
     "d2q9_1024_fp32_force": (9, 1, 1, 0, (1024, 1024), 0.56, 0.01, 1.0, 28.0, 0.0),
 }
+# residual target of the FP32 uneven batch: 2.5x above the highest FP32
+# floor seen among its 512 problems (about 2e-8)
+UNEVEN_TOL_F32 = 5e-8
 KERNEL_SOURCES = ["paper_0710_5470_amd/csrc/lbm_step.h", "paper_0710_5470_amd/csrc/lbm_force.h",
                   "paper_0710_5470_amd/csrc/lbm_lattice.h"]
 
@@ -181,6 +186,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched time-to-steady leg (warm vs cold)")
+    ap.add_argument("--no-uneven", action="store_true",
+                    help="skip the uneven 512-drop batch leg (FP32 and FP64 storage)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="instead: time a plain device copy of this many bytes (HBM counter "
                          "calibration for rocprofv3 --pmc)")
@@ -272,6 +279,15 @@ def main():
         # residual 1e-10), cold start versus the shipped warm-start network
         from paper_0710_5470_amd import warmstart
         out["batched_time_to_steady"] = warmstart.time_to_steady()
+    if not args.no_uneven:
+        # 512 drops on uneven square lattices (side 32..256, seed 4), cold
+        # start: FP32 storage to a residual above its rounding floor, and FP64
+        # storage to 1e-10
+        from paper_0710_5470_amd import drops
+        sp = drops.specs()
+        out["uneven_batch_time_to_steady"] = [
+            drops.time_to_steady(sp, lbm.STORE_F32_SHIFTED, lbm.COMPUTE_NATIVE, tol=UNEVEN_TOL_F32),
+            drops.time_to_steady(sp, lbm.STORE_F64, lbm.COMPUTE_NATIVE, tol=1e-10)]
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(out), flush=True)

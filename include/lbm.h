@@ -217,7 +217,11 @@ int lbm_batch_init(lbm_batch **out, int nprob, const lbm_params *per_problem,
                    void *dev_workspace, size_t bytes, void *stream,
                    const double *dev_rho0, const double *dev_u0);
 
-/* Advance every active problem by nsteps (no checks).  Only enqueues. */
+/* Advance every active problem by nsteps (no checks).  Only enqueues.
+ * A problem that lbm_batch_run retired is skipped and keeps its state; its
+ * populations stay in the buffer the batch returns to after an even number
+ * of steps, so while any problem is retired an odd nsteps is refused with
+ * LBM_E_STATE (lbm_batch_reactivate lifts this). */
 int lbm_batch_step(lbm_batch *bt, long long nsteps);
 
 /* Run until no problem is active or max_steps more steps have been taken.

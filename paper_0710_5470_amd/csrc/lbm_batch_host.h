@@ -32,6 +32,7 @@ struct lbm_batch {
     bool graph_ok;
     int cur;
     long long steps;
+    bool all_active;  // false once lbm_batch_run has retired a problem
 };
 
 namespace {
@@ -298,6 +299,7 @@ int lbm_batch_init(lbm_batch **out, int nprob, const lbm_params *pp, void *dev_w
     lbm_batch *bt = new (std::nothrow) lbm_batch();
     if (!bt) return LBM_E_NOMEM;
     bt->nprob = nprob;
+    bt->all_active = true;
     bt->base = pp[0];
     bt->pp.assign(pp, pp + nprob);
     bt->stream = static_cast<hipStream_t>(stream);
@@ -395,6 +397,9 @@ int lbm_batch_init(lbm_batch **out, int nprob, const lbm_params *pp, void *dev_w
 int lbm_batch_step(lbm_batch *bt, long long nsteps)
 {
     if (!bt || nsteps < 0) return LBM_E_INVAL;
+    // A retired problem is skipped, so its state stays in the buffer it was
+    // in; an odd count would leave the active problems in the other one.
+    if ((nsteps & 1) && !bt->all_active) return LBM_E_STATE;
     for (long long s = 0; s < nsteps; s++) batch_step(bt, 1, 0, nullptr, nullptr, bptr<int>(bt, bt->o_act));
     bt->steps += nsteps;
     return hipGetLastError() == hipSuccess ? LBM_OK : LBM_E_DEVICE;
@@ -426,6 +431,7 @@ int lbm_batch_run(lbm_batch *bt, double tol, int check_every, long long max_step
             return LBM_E_DEVICE;
     }
     bt->steps += done;
+    bt->all_active = h_count == bt->nprob;
     if (bt->cp != cp0) {  // the caller's launch again for later calls
         bt->cp = cp0;
         if ((rc = batch_items(bt)) != LBM_OK) return rc;
@@ -458,6 +464,7 @@ int lbm_batch_reactivate(lbm_batch *bt)
                        bt->stream) != hipSuccess ||
         hipStreamSynchronize(bt->stream) != hipSuccess)
         return LBM_E_DEVICE;
+    bt->all_active = true;
     return LBM_OK;
 }
 

@@ -424,7 +424,8 @@ template <class L, class S> int totals_t(lbm_ctx *c, double *mass, double *mom)
     return LBM_OK;
 }
 
-// Maxwell construction by Newton's method on (p(g) - p(l), mu(g) - mu(l))
+// van der Waals pressure p0(rho) of Eq. (p0), its derivative and the chemical
+// potential, for the Maxwell construction in lbm_coexistence (bisections)
 double vdw_p(double a, double b, double T, double r) { return r * T / (1 - b * r) - a * r * r; }
 double vdw_dp(double a, double b, double T, double r)
 {

@@ -129,6 +129,43 @@ def test_reactivated_batch_continues_to_a_tighter_residual():
         assert torch.equal(seg, r_one)
 
 
+def test_odd_step_count_refused_while_a_problem_is_retired():
+    """A retired problem is skipped and keeps its populations in the buffer
+    the batch returns to after an even number of steps.  After a run has
+    retired problems, lbm_batch_step refuses an odd count (LBM_E_STATE) and
+    an even count changes nothing; after lbm_batch_reactivate an odd count is
+    accepted and continues every problem from its retired state (equal to a
+    single-problem run of the same total number of steps)."""
+    from paper_0710_5470_amd import lbm
+    specs = [SPECS[4], SPECS[1]]
+    plist, rho = _problems(specs, 0, 0)
+    bt = lbm.Batch(plist, rho)
+    _say("odd steps after retirement")
+    # every problem retires, converged or at max_steps
+    steps, _, status = bt.run(tol=1e-7, check_every=50, max_steps=4000)
+    _say("  run", steps, status)
+    assert all(st in (lbm.BATCH_CONVERGED, lbm.BATCH_MAXSTEPS) for st in status)
+    r0, v0 = bt.moments()
+    with pytest.raises(lbm.LBMError) as ei:
+        bt.step(1)
+    assert ei.value.code == lbm.E_STATE
+    bt.step(2)
+    r1, v1 = bt.moments()
+    assert torch.equal(r0, r1) and torch.equal(v0, v1)
+    bt.reactivate()
+    bt.step(1)
+    r2, _ = bt.moments()
+    bt.close()
+    for k in range(2):
+        p1, rr = _problems(specs[k:k + 1], 0, 0)
+        one = lbm.Batch(p1, rr)
+        one.step(steps[k] + 1)
+        r_one, _ = one.moments()
+        one.close()
+        seg = r2[sum(p.nx * p.ny for p in plist[:k]):][:plist[k].nx * plist[k].ny]
+        assert torch.equal(seg, r_one)
+
+
 def test_full_size_batch_matches_oracle_on_sampled_problems():
     """The batched time-to-steady workload at full size (512 drops of 128^2,
     FP64, tau = 1) in the launch the batch autotuner picks for it, 6 steps;
@@ -159,3 +196,52 @@ def test_full_size_batch_matches_oracle_on_sampled_problems():
         _say("problem %d: rel err rho %.2e, abs err u %.2e" % (k, er, ev))
         assert er < 1e-12 and ev < 1e-12
     bt.close()
+
+
+def test_uneven_fp32_batch_matches_oracle_on_sampled_problems():
+    """The uneven batched workload at full size (512 drops, side 32..256,
+    FP32 storage and arithmetic, tau = 1; paper_0710_5470_amd.drops) in the
+    launch the batch autotuner picks for it, 50 steps; five sampled problems
+    (first, last, the smallest, the largest and one of odd side) against the
+    oracle's FP64 runs of them.  The FP32 parity bar: 1e-5 relative on rho;
+    on u, 2e-8 absolute for rest deviations |delta_0| = |f_0 - s_0| below 2,
+    scaled with the FP32 rounding unit at the largest |delta_0| of the
+    problem (the velocity error comes from roundings of delta_0; the single
+    lattice parity tests at T = 0.56 have |delta_0| < 2).  At T in
+    [0.54, 0.55] the phases are further apart and |delta_0| reaches 2..4,
+    where an FP32 ulp is twice as large: 4e-8."""
+    import oracle
+    from paper_0710_5470_amd import autotune, drops, lbm
+    sp = drops.specs()
+    plist, rho0 = drops.problems(sp)
+    sides = np.array([s["side"] for s in sp])
+    launch = autotune.autotune_batch(plist, rho0, use_cache=False)
+    _say("uneven FP32 batch, 512 drops, %d sites, launch %s" % (int((sides ** 2).sum()), launch))
+    bt = lbm.Batch(plist, rho0)
+    bt.set_launch(*launch)
+    bt.step(50)
+    r, v = bt.moments()
+    rs, vs = bt.split(r), bt.split(v)
+    bt.close()
+    r0 = rho0.cpu().numpy()
+    off = np.concatenate([[0], np.cumsum(sides ** 2)])
+    odd = int(np.nonzero(sides % 2 == 1)[0][0])
+    picks = sorted({0, len(sp) - 1, int(np.argmin(sides)), int(np.argmax(sides)), odd})
+    for k in picks:
+        n, s = int(sides[k]), sp[k]
+        op = oracle.params(q=9, scheme=0, shape=(n, n), T=s["T"], kappa=s["kappa"], tau=1.0)
+        f0 = oracle.init(op, r0[off[k]:off[k + 1]].reshape(n, n))
+        f1 = oracle.run(op, f0, 50)
+        ro, vo = oracle.observe(op, f1)
+        rg, vg = rs[k].cpu().numpy(), vs[k].cpu().numpy()
+        er = float(np.max(np.abs(rg - ro) / ro))
+        ev = float(np.max(np.abs(vg[:2] - vo[:2])))
+        # the shift of the rest population: its rest equilibrium at the mean
+        # initial density
+        s0 = oracle.feq_site(op, float(np.mean(f0.sum(0))), np.zeros(3), np.zeros(3), 0.0)[0]
+        d0 = max(float(np.abs(f0[0] - s0).max()), float(np.abs(f1[0] - s0).max()))
+        tol_v = 2e-8 * max(1.0, 2.0 ** np.floor(np.log2(d0)))
+        _say("problem %d (side %d, T %.4f): rel err rho %.2e, abs err u %.2e (tol %.0e, "
+             "max|delta_0| %.2f), max|u| %.2e" % (k, n, s["T"], er, ev, tol_v, d0,
+                                                 float(np.abs(vo).max())))
+        assert er < 1e-5 and ev < tol_v

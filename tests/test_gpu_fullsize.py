@@ -95,3 +95,56 @@ def test_full_size_step_matches_oracle_on_sampled_sites(wl, tol):
           % (wl, len(xyz), worst, tol, float(np.abs(f1).max())), flush=True)
     assert np.isfinite(f1).all()
     assert worst < tol
+
+
+EPS32 = 2.0 ** -24  # FP32 unit roundoff
+
+
+def test_benchmark_workload_keeps_its_invariants_over_5000_steps():
+    """The benchmarked workload (D3Q19 256^3, FP32 storage and arithmetic,
+    forcing scheme, tau = 0.8) for 5000 steps in the autotuned launch: the
+    state stays finite, the spurious velocity stays small, and the mass and
+    momentum totals (reduced in FP64 from the stored deviations) move by no
+    more than FP32 rounding allows.  In exact arithmetic the collision keeps
+    each site's mass and, for the forcing scheme, the total momentum (the
+    body force of Appendix A sums to zero over a periodic lattice), and the
+    drop starts at rest, so the initial momentum is zero.  Bound, as in the
+    reduction tests: every step rounds each stored deviation once and the
+    collision adds a few roundings of the same size, so a total can move by
+    at most 4 * steps * EPS32 * sum_r sum_i |delta_i| (taken at the start and
+    at the end, whichever is larger)."""
+    import bench
+    from paper_0710_5470_amd import autotune, lbm
+    wl = "d3q19_256_fp32_force"
+    print("[gpu-case] 5000-step invariants", wl, flush=True)
+    p, rho0 = bench.make_workload(wl)
+    sim = lbm.Simulation(p, rho0)
+    autotune.autotune(sim, use_cache=False)
+    print("[gpu-case] launch", sim.launch(), flush=True)
+    shift = torch.tensor(sim.shift(), dtype=torch.float64, device="cuda")
+
+    def abs_dev():
+        f = sim.get_state()
+        return float((f - shift[:, None]).abs().sum())
+
+    m0, j0 = sim.invariants()
+    d0 = abs_dev()
+    v0 = sim.max_spurious_u()
+    steps = 5000
+    for k in range(10):
+        sim.step(steps // 10)
+        vmax = sim.max_spurious_u()  # raises LBMError on a non-finite state
+        print("[gpu-case]   step %d max|v| %.3e" % ((k + 1) * steps // 10, vmax), flush=True)
+        assert vmax < 0.05
+    m1, j1 = sim.invariants()
+    d1 = abs_dev()
+    sim.close()
+    bound = 4.0 * steps * EPS32 * max(d0, d1)
+    dm = abs(m1 - m0)
+    dj = float(np.max(np.abs(np.array(j1) - np.array(j0))))
+    print("[gpu-case] mass %.10e -> %.10e (drift %.3e, relative %.2e), |momentum| %.3e -> %.3e, "
+          "bound %.3e, max|v| %.3e -> %.3e"
+          % (m0, m1, dm, dm / m0, float(np.max(np.abs(j0))), float(np.max(np.abs(j1))), bound,
+             v0, vmax), flush=True)
+    assert np.max(np.abs(j0)) <= 1e-9 * m0
+    assert dm <= bound and dj <= bound
