@@ -69,7 +69,8 @@ enum {
     LBM_E_NOMEM = -2,     /* workspace smaller than lbm_workspace_bytes()  */
     LBM_E_DEVICE = -3,    /* a HIP call or kernel launch failed            */
     LBM_E_NONFINITE = -4, /* non-finite value or b*rho >= 1 in the state   */
-    LBM_E_STATE = -5      /* call not valid in the context's current state */
+    LBM_E_STATE = -5,     /* call not valid in the context's current state */
+    LBM_E_LIMIT = -6      /* input beyond the fixed scratch of an allocation-free call */
 };
 
 typedef struct {
@@ -309,6 +310,24 @@ size_t lbm_net_conv3x3_bwd_weight_workspace(const lbm_conv_shape *s);
 int lbm_net_conv3x3_bwd_weight(const lbm_conv_shape *s, const float *dev_dout, const float *dev_in,
                                int relu_in, float *dev_dw, float *dev_dbias, void *dev_workspace,
                                size_t bytes, void *stream);
+
+/* Allocation-free variant of lbm_net_conv3x3_bwd_weight, for callers that
+ * cannot allocate device memory (code under HIP graph capture, serving
+ * loops, hosts that forbid hipMalloc): the same kernels, the same partial
+ * sums and the same fixed summation order, so dW and dbias are bitwise those
+ * of lbm_net_conv3x3_bwd_weight.  The per-workgroup partials live in a fixed
+ * 16 MiB device array of the library (one per GPU, held until the process
+ * ends) instead of a caller workspace; the call allocates nothing, host or
+ * device.  Returns LBM_E_LIMIT, before any device work, when the partials
+ * would exceed it: lbm_net_conv3x3_bwd_weight_workspace(s) > 16 MiB
+ * (nb*h*w <= 463,872 pixels at cin = cout = 32).  The array is shared by
+ * every call on a GPU and keeps the last call's contents (every call writes
+ * all the partials it reads): calls that overlap on one GPU (other streams,
+ * other threads) race and must be serialised by the caller.  stream must
+ * belong to the current device. */
+int lbm_net_conv3x3_bwd_weight_noalloc(const lbm_conv_shape *s, const float *dev_dout,
+                                       const float *dev_in, int relu_in, float *dev_dw,
+                                       float *dev_dbias, void *stream);
 
 /* Mean squared error over the first creal of c channels of npix pixels;
  * writes grad = 2 (pred - target) / (npix creal) (zero in padded channels)

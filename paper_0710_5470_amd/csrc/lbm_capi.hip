@@ -508,6 +508,7 @@ const char *lbm_strerror(int code)
     case LBM_E_DEVICE: return "HIP call or kernel launch failed";
     case LBM_E_NONFINITE: return "non-finite state or b*rho >= 1";
     case LBM_E_STATE: return "call not valid in the current state";
+    case LBM_E_LIMIT: return "input beyond the fixed scratch of an allocation-free call";
     default: return "unknown status";
     }
 }

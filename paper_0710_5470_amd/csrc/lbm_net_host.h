@@ -1,10 +1,40 @@
 // lbm_net_host.h -- host side of the warm-start network kernels (included
 // once, at the end of lbm_capi.hip).
 
+#include <mutex>
+
 #include "lbm_net.h"
 #include "lbm_warm.h"
 
+// Device scratch of lbm_net_conv3x3_bwd_weight_noalloc: the per-workgroup
+// partials of the weight gradient.  Every GPU holds its own copy at its own
+// address; host code never passes this name to a kernel (on the host it is
+// only a stand-in for the symbol) but the address that hipGetSymbolAddress
+// returns for the current device.
+constexpr size_t NET_SCRATCH_BYTES = size_t(16) << 20;
+static __device__ __align__(256) float scratch[NET_SCRATCH_BYTES / sizeof(float)];
+
 namespace {
+
+constexpr int NET_SCRATCH_DEVICES = 64;
+std::mutex net_scratch_mu;
+void *net_scratch_ptr[NET_SCRATCH_DEVICES];  // per device, looked up once
+
+// Device address of `scratch` on the current device (looked up on the
+// first call on that device, with that device current).
+int net_scratch(void **out)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= NET_SCRATCH_DEVICES) return LBM_E_DEVICE;
+    std::lock_guard<std::mutex> lock(net_scratch_mu);
+    if (!net_scratch_ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return LBM_E_DEVICE;
+        net_scratch_ptr[dev] = p;
+    }
+    *out = net_scratch_ptr[dev];
+    return LBM_OK;
+}
 
 bool conv_ok(const lbm_conv_shape *s)
 {
@@ -62,22 +92,50 @@ size_t lbm_net_conv3x3_bwd_weight_workspace(const lbm_conv_shape *s)
     return size_t(parts) * (9 * s->cout * s->cin + s->cout) * sizeof(float);
 }
 
-int lbm_net_conv3x3_bwd_weight(const lbm_conv_shape *s, const float *dev_dout, const float *dev_in,
-                               int relu_in, float *dev_dw, float *dev_db, void *dev_ws, size_t ws_bytes,
-                               void *stream)
+} // extern "C"
+
+namespace {
+
+// Weight gradient with the per-workgroup partials in `part` (at least
+// lbm_net_conv3x3_bwd_weight_workspace(s) bytes): one workgroup per
+// NET_CHUNK pixels, then a fixed-order sum of the partials.
+int bwd_weight_launch(const lbm_conv_shape *s, const float *dev_dout, const float *dev_in, int relu_in,
+                      float *dev_dw, float *dev_db, float *part, hipStream_t st)
 {
-    if (!conv_ok(s) || !dev_dout || !dev_in || !dev_dw || !dev_db || !dev_ws) return LBM_E_INVAL;
-    if (ws_bytes < lbm_net_conv3x3_bwd_weight_workspace(s)) return LBM_E_NOMEM;
-    hipStream_t st = static_cast<hipStream_t>(stream);
     long long npix = (long long)s->nb * s->h * s->w;
     int parts = int((npix + NET_CHUNK - 1) / NET_CHUNK);
-    float *part = static_cast<float *>(dev_ws);
     lbmnet::conv_bwd_weight_kernel<<<parts, lbmnet::NET_THREADS, 0, st>>>(conv_shape(s), dev_dout, dev_in,
                                                                           relu_in, NET_CHUNK, part);
     const int nw = 9 * s->cout * s->cin;
     const int len = nw + s->cout;  // weight gradient, then bias gradient
     lbmnet::sum_parts_kernel<<<(len + 63) / 64, 256, 0, st>>>(parts, len, nw, part, dev_dw, dev_db);
     return hipGetLastError() == hipSuccess ? LBM_OK : LBM_E_DEVICE;
+}
+
+} // namespace
+
+extern "C" {
+
+int lbm_net_conv3x3_bwd_weight(const lbm_conv_shape *s, const float *dev_dout, const float *dev_in,
+                               int relu_in, float *dev_dw, float *dev_db, void *dev_ws, size_t ws_bytes,
+                               void *stream)
+{
+    if (!conv_ok(s) || !dev_dout || !dev_in || !dev_dw || !dev_db || !dev_ws) return LBM_E_INVAL;
+    if (ws_bytes < lbm_net_conv3x3_bwd_weight_workspace(s)) return LBM_E_NOMEM;
+    return bwd_weight_launch(s, dev_dout, dev_in, relu_in, dev_dw, dev_db, static_cast<float *>(dev_ws),
+                             static_cast<hipStream_t>(stream));
+}
+
+int lbm_net_conv3x3_bwd_weight_noalloc(const lbm_conv_shape *s, const float *dev_dout, const float *dev_in,
+                                       int relu_in, float *dev_dw, float *dev_db, void *stream)
+{
+    if (!conv_ok(s) || !dev_dout || !dev_in || !dev_dw || !dev_db) return LBM_E_INVAL;
+    if (lbm_net_conv3x3_bwd_weight_workspace(s) > NET_SCRATCH_BYTES) return LBM_E_LIMIT;
+    void *part = nullptr;
+    int rc = net_scratch(&part);
+    if (rc != LBM_OK) return rc;
+    return bwd_weight_launch(s, dev_dout, dev_in, relu_in, dev_dw, dev_db, static_cast<float *>(part),
+                             static_cast<hipStream_t>(stream));
 }
 
 int lbm_net_mse(long long npix, int c, int creal, const float *dev_pred, const float *dev_target,

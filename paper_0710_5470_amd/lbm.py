@@ -21,7 +21,7 @@ SCHEME_EQ, SCHEME_FORCE = 0, 1
 STORE_F64, STORE_F32_SHIFTED = 0, 1
 SHIFT_REST_EQ, SHIFT_WEIGHTS = 0, 1
 COMPUTE_NATIVE, COMPUTE_F64 = 0, 1
-OK, E_INVAL, E_NOMEM, E_DEVICE, E_NONFINITE, E_STATE = 0, -1, -2, -3, -4, -5
+OK, E_INVAL, E_NOMEM, E_DEVICE, E_NONFINITE, E_STATE, E_LIMIT = 0, -1, -2, -3, -4, -5, -6
 
 
 class lbm_params(ctypes.Structure):
@@ -103,6 +103,8 @@ _sig.update({
     "lbm_net_conv3x3_bwd_weight_workspace": (ctypes.c_size_t, [_cs]),
     "lbm_net_conv3x3_bwd_weight": (ctypes.c_int, [_cs, _vp, _vp, ctypes.c_int, _vp, _vp, _vp,
                                                   ctypes.c_size_t, _vp]),
+    "lbm_net_conv3x3_bwd_weight_noalloc": (ctypes.c_int, [_cs, _vp, _vp, ctypes.c_int, _vp, _vp,
+                                                          _vp]),
     "lbm_net_mse": (ctypes.c_int, [ctypes.c_longlong, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp,
                                    _vp, _dp, _vp]),
     "lbm_net_adam": (ctypes.c_int, [ctypes.c_int, _vp, _vp, _vp, _vp, ctypes.c_double,
@@ -354,6 +356,14 @@ def lbm_net_conv3x3_bwd_weight(shape, dout, x, relu_in, dw, db, ws, stream=None)
                                          _ptr(dw), _ptr(db), _ptr(ws),
                                          ws.numel() * ws.element_size(), _stream(stream)),
            "lbm_net_conv3x3_bwd_weight")
+
+
+def lbm_net_conv3x3_bwd_weight_noalloc(shape, dout, x, relu_in, dw, db, stream=None):
+    """The weight gradient with the partials in the library's fixed device
+    scratch (no workspace argument, nothing allocated)."""
+    _check(_L.lbm_net_conv3x3_bwd_weight_noalloc(ctypes.byref(shape), _ptr(dout), _ptr(x),
+                                                 int(relu_in), _ptr(dw), _ptr(db), _stream(stream)),
+           "lbm_net_conv3x3_bwd_weight_noalloc")
 
 
 def lbm_net_mse(npix, c, creal, pred, target, grad, part, want_loss=True, stream=None):
