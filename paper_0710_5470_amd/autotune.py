@@ -27,7 +27,8 @@ def _key(p):
 
 def candidates(p):
     np_ = p.nz if p.lattice == lbm.D3Q19 else p.ny
-    planes = sorted(set(min(c, np_) for c in (8, 16, 32, 64, 128, 256)))
+    short = (4,) if p.lattice == lbm.D2Q9 else ()  # D2Q9: rows are short, 4-row marches pay
+    planes = sorted(set(min(c, np_) for c in short + (8, 16, 32, 64, 128, 256)))
     return [(t, c) for t in range(lbm.lbm_tile_count(p.lattice)) for c in planes]
 
 
@@ -100,7 +101,8 @@ def batch_candidates(plist):
     e.g. 3 chunks of 43 planes for 128^2 problems)."""
     p = plist[0]
     np_max = max(q.nz if q.lattice == lbm.D3Q19 else q.ny for q in plist)
-    planes = set(min(c, np_max) for c in (8, 16, 32, 64))
+    short = (4,) if p.lattice == lbm.D2Q9 else ()
+    planes = set(min(c, np_max) for c in short + (8, 16, 32, 64))
     planes |= set(-(-np_max // k) for k in range(1, 9) if -(-np_max // k) >= 8)
     return [(t, c) for t in range(lbm.lbm_tile_count(p.lattice)) for c in sorted(planes)]
 

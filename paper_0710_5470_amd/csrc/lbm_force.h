@@ -31,6 +31,11 @@ namespace lbm {
 #ifndef LBM_FORCE_DMA
 #define LBM_FORCE_DMA 1
 #endif
+// D2Q9 keeps the register march (short marches, see lbm_step.h): 1024^2 FP32
+// forcing 0.0196 against 0.0243 ms per step.
+#ifndef LBM_FORCE_DMA_2D
+#define LBM_FORCE_DMA_2D 0
+#endif
 
 template <class L, class S, class R, int TX, int TY>
 __device__ __forceinline__ void force_tile(const Job<R> &J, const Coefs<R> &c)
@@ -57,7 +62,7 @@ __device__ __forceinline__ void force_tile(const Job<R> &J, const Coefs<R> &c)
     // lc + 3 is taken into registers (see below); needs every halo site in
     // one pass of the threads and the staging to fit the LDS.
     constexpr int SPL = Q * NT;                    // floats per staging plane
-    constexpr bool DMA = LBM_FORCE_DMA && sizeof(S) == 4 &&
+    constexpr bool DMA = LBM_FORCE_DMA && (DIM == 3 || LBM_FORCE_DMA_2D) && sizeof(S) == 4 &&
                          2 * SPL * 4 + (NR * PL + NTC * GPL) * sizeof(R) <= 160 * 1024;
 
     __shared__ R rho_s[NR * PL];

@@ -618,6 +618,13 @@ namespace lbm {
 #ifndef LBM_EQ_DMA
 #define LBM_EQ_DMA 1
 #endif
+// D2Q9 keeps the register march: its staging plane is a single row, the
+// autotuned marches are short (4-16 rows per work item) and the staging's
+// deeper prologue costs more than it hides (batched uneven D2Q9 FP32 drops:
+// 0.366 against 0.397 ms per full-batch step).
+#ifndef LBM_EQ_DMA_2D
+#define LBM_EQ_DMA_2D 0
+#endif
 
 // The step of one tile: the forcing scheme's march (lbm_force.h) or the
 // equilibrium scheme's (FP32 storage: with staged loads).
@@ -626,7 +633,8 @@ __device__ __forceinline__ void tile_step(const Job<R> &J, const Coefs<R> &c)
 {
     constexpr int NT = TX * TY, Q = L::Q, PLE = (TX + 2) * (TY + (L::DIM == 3 ? 2 : 0));
     constexpr bool EQ_DMA =
-        LBM_EQ_DMA && sizeof(S) == 4 && (2 * Q * NT * 4 + 4 * PLE * int(sizeof(R))) <= 160 * 1024;
+        LBM_EQ_DMA && (L::DIM == 3 || LBM_EQ_DMA_2D) && sizeof(S) == 4 &&
+        (2 * Q * NT * 4 + 4 * PLE * int(sizeof(R))) <= 160 * 1024;
     if constexpr (SCHEME == SCHEME_FORCE)
         force_tile<L, S, R, TX, TY>(J, c);
     else if constexpr (EQ_DMA)

@@ -80,6 +80,61 @@ def test_network_gradient_matches_reference():
         assert np.linalg.norm(db.cpu().numpy() - dbr) / np.linalg.norm(dbr) < 2e-2
 
 
+def test_network_layers_match_reference_layer_by_layer():
+    """The same network, layer by layer: each GPU layer (forward, data
+    gradient, weight and bias gradient) against the FP64 reference applied
+    to the GPU's own inputs of that layer (its input activation, and the
+    gradient arriving from the layer above), with the same bf16 rounding of
+    the matrix-core operands.  Without the compounding of bf16 roundings
+    through six layers, every layer meets the single-convolution bar of
+    1e-4 relative; the loss gradient of the output meets 1e-6."""
+    from oracle import convnet
+    from paper_0710_5470_amd import lbm, warmstart
+    net = warmstart.WarmNet(seed=3)
+    rng = np.random.default_rng(9)
+    x = np.zeros((2, 32, 32, 16), dtype=np.float32)
+    x[..., :6] = rng.normal(0, 1, (2, 32, 32, 6))
+    y = np.zeros((2, 32, 32, 16), dtype=np.float32)
+    y[..., :3] = rng.normal(0, 1, (2, 32, 32, 3))
+    dev = torch.device("cuda")
+    zs = net.forward(torch.tensor(x, device=dev))
+    params = net.numpy_params()
+    zn = [z.cpu().numpy().astype(np.float64) for z in zs]
+    for l, (W, b) in enumerate(params):
+        ref = convnet.conv_fwd(zn[l], W, b, relu_in=l > 0, round_bf16=True)
+        creal = warmstart.LAYERS[l][2]
+        ref[..., creal:] = 0.0
+        e = _rel(zn[l + 1], ref)
+        _say("layer %d forward rel err %.2e" % (l, e))
+        assert e < 1e-4
+    n = 2 * 32 * 32
+    g = torch.empty_like(zs[-1])
+    part = torch.empty(1024, dtype=torch.float64, device=dev)
+    lbm.lbm_net_mse(n, warmstart.CP_OUT, warmstart.OUT_REAL, zs[-1], torch.tensor(y, device=dev),
+                    g, part)
+    _, g_ref = convnet.mse(zn[-1], y.astype(np.float64), warmstart.OUT_REAL)
+    assert _rel(g.cpu().numpy(), g_ref) < 1e-6
+    d = g
+    for l in range(len(params) - 1, -1, -1):
+        W, b = net.params[l]
+        s = net._shape(2, 32, 32, l)
+        ws = torch.empty(lbm.lbm_net_conv3x3_bwd_weight_workspace(s), dtype=torch.uint8, device=dev)
+        dW, db = torch.empty_like(W), torch.empty_like(b)
+        lbm.lbm_net_conv3x3_bwd_weight(s, d, zs[l], l > 0, dW, db, ws)
+        da_r, dW_r, db_r = convnet.conv_bwd(zn[l], params[l][0], d.cpu().numpy().astype(np.float64),
+                                            relu_in=l > 0, round_bf16=True)
+        e = [_rel(dW.cpu().numpy(), dW_r), _rel(db.cpu().numpy(), db_r)]
+        if l > 0:
+            din = torch.empty_like(zs[l])
+            lbm.lbm_net_conv3x3_bwd_data(s, d, W, zs[l], din)
+            torch.cuda.synchronize()
+            e.append(_rel(din.cpu().numpy(), da_r))
+            d = din
+        _say("layer %d backward rel err weight %.2e bias %.2e%s"
+             % (l, e[0], e[1], " data %.2e" % e[2] if l > 0 else ""))
+        assert max(e) < 1e-4
+
+
 def test_training_reduces_loss():
     from paper_0710_5470_amd import warmstart
     net = warmstart.WarmNet(seed=5)

@@ -48,3 +48,18 @@ def test_tau_scan_minimum_near_s_zero(scans):
     assert 0.65 <= d["argmin"] <= 0.95
     # growth at large tau (S grows like tau^3)
     assert d["umax"][-1] > 3.0 * min(d["umax"])
+
+
+def test_earlier_weight_choices_worse_than_optimum(scans):
+    """Section "Determining a unique equilibrium distribution" notes that
+    earlier schemes used w^xx_5-8 = 0 (Inamuro et al.) and -1/72 (Desplat et
+    al.) instead of the optimum -1/24: both leave larger spurious velocities
+    at the paper's drop setup."""
+    d = scans["wxx_5_8"]
+    v, u = np.array(d["values"]), np.array(d["umax"])
+    at = lambda x: float(u[int(np.argmin(np.abs(v - x)))])
+    assert np.min(np.abs(v - 0.0)) < 1e-12 and np.min(np.abs(v + 1.0 / 72.0)) < 1e-12
+    u_opt, u_inamuro, u_desplat = at(-1.0 / 24.0), at(0.0), at(-1.0 / 72.0)
+    print("[gpu-case] wxx_5_8: optimum %.3e, Inamuro (0) %.3e (x%.2f), Desplat (-1/72) %.3e (x%.2f)"
+          % (u_opt, u_inamuro, u_inamuro / u_opt, u_desplat, u_desplat / u_opt), flush=True)
+    assert u_inamuro > u_opt and u_desplat > u_opt
