@@ -43,7 +43,8 @@ WORKLOADS = {
 # floor seen among its 512 problems (about 2e-8)
 UNEVEN_TOL_F32 = 5e-8
 KERNEL_SOURCES = ["paper_0710_5470_amd/csrc/lbm_step.h", "paper_0710_5470_amd/csrc/lbm_force.h",
-                  "paper_0710_5470_amd/csrc/lbm_lattice.h"]
+                  "paper_0710_5470_amd/csrc/lbm_lattice.h", "paper_0710_5470_amd/csrc/lbm_step3d.hip",
+                  "paper_0710_5470_amd/build.py"]
 
 
 def make_workload(wl):

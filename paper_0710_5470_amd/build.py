@@ -13,24 +13,46 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIBDIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(LIBDIR, "liblbm.so")
-SOURCES = [os.path.join(HERE, "csrc", "lbm_capi.hip")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 HIP_FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-ffp-contract=on", "-Wall", "-Wno-unused-function",
     "-I" + os.path.join(ROOT, "include"),
 ]
+# translation units and their extra flags: the D3Q19 step kernels are
+# scheduled for instruction-level parallelism (faster there, slower for the
+# batched D2Q9 kernels of the main unit)
+UNITS = [(os.path.join(HERE, "csrc", "lbm_capi.hip"), []),
+         (os.path.join(HERE, "csrc", "lbm_step3d.hip"), ["-mllvm", "--amdgpu-sched-strategy=max-ilp"])]
+SOURCES = [u[0] for u in UNITS]
 
 
-def build(verbose=False, extra=(), out=LIB):
-    os.makedirs(os.path.dirname(out), exist_ok=True)
-    tmp = out + ".tmp"
-    cmd = [HIPCC] + HIP_FLAGS + list(extra) + SOURCES + ["-o", tmp]
+def _run(cmd, verbose):
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
+
+
+def build(verbose=False, extra=(), out=LIB):
+    """Compile every unit to an object (in parallel) and link the library."""
+    os.makedirs(os.path.dirname(out), exist_ok=True)
+    tmp = out + ".tmp"
+    objs, procs = [], []
+    for src, flags in UNITS:
+        obj = "%s.%s.o" % (out, os.path.splitext(os.path.basename(src))[0])
+        cmd = [HIPCC] + HIP_FLAGS + flags + list(extra) + ["-c", src, "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append((subprocess.Popen(cmd), cmd))
+        objs.append(obj)
+    for p, cmd in procs:
+        if p.wait() != 0:
+            raise subprocess.CalledProcessError(p.returncode, cmd)
+    _run([HIPCC, "--offload-arch=gfx950", "-fPIC", "-shared"] + objs + ["-o", tmp], verbose)
+    for obj in objs:
+        os.remove(obj)
     os.replace(tmp, out)
     return out
 

@@ -18,6 +18,14 @@
 
 using namespace lbm;
 
+// the D3Q19 step kernels come from lbm_step3d.hip
+namespace lbm {
+#define LBM_STEP3D_EXTERN(SCH, S, R, TX, TY) \
+    extern template __global__ void step_kernel<D3Q19, SCH, S, R, TX, TY>(StepArgs<R>);
+LBM_STEP3D_INSTANCES(LBM_STEP3D_EXTERN)
+#undef LBM_STEP3D_EXTERN
+} // namespace lbm
+
 namespace {
 
 constexpr int RED_BLOCKS = 1024;

@@ -741,3 +741,14 @@ void batch_step_kernel(BatchArgs<R> B)
 }
 
 } // namespace lbm
+
+// The D3Q19 instances of step_kernel (every launch shape and arithmetic):
+// instantiated in lbm_step3d.hip, a translation unit of their own that the
+// build compiles with another machine-scheduler strategy, and declared
+// extern where they are launched.
+#define LBM_STEP3D_SHAPES(X, SCH, S, R) \
+    X(SCH, S, R, 64, 4) X(SCH, S, R, 32, 8) X(SCH, S, R, 64, 8) X(SCH, S, R, 32, 16) X(SCH, S, R, 128, 4)
+#define LBM_STEP3D_INSTANCES(X)                                                                   \
+    LBM_STEP3D_SHAPES(X, 0, double, double) LBM_STEP3D_SHAPES(X, 0, float, float)                \
+    LBM_STEP3D_SHAPES(X, 0, float, double) LBM_STEP3D_SHAPES(X, 1, double, double)               \
+    LBM_STEP3D_SHAPES(X, 1, float, float) LBM_STEP3D_SHAPES(X, 1, float, double)
