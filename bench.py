@@ -37,6 +37,8 @@ WORKLOADS = {
     "d3q19_256_fp64_force": (19, 1, 0, 0, (256, 256, 256), 0.56, 0.02, 0.8, 48.0, 0.01),
     "d3q19_256_fp32_eq": (19, 0, 1, 0, (256, 256, 256), 0.56, 0.02, 0.8, 48.0, 0.01),
     "d2q9_1024_fp64_eq": (9, 0, 0, 0, (1024, 1024), 0.56, 0.01, 1.0, 28.0, 0.0),
+    "d2q9_1024_fp64_force": (9, 1, 0, 0, (1024, 1024), 0.56, 0.01, 1.0, 28.0, 0.0),
+    "d2q9_1024_fp32_eq": (9, 0, 1, 0, (1024, 1024), 0.56, 0.01, 1.0, 28.0, 0.0),
     "d2q9_1024_fp32_force": (9, 1, 1, 0, (1024, 1024), 0.56, 0.01, 1.0, 28.0, 0.0),
 }
 # residual target of the FP32 uneven batch: 2.5x above the highest FP32

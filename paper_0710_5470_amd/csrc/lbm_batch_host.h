@@ -95,10 +95,12 @@ int batch_items(lbm_batch *bt)
         P.nx = bt->gnx[k];
         P.ny = bt->gny[k];
         P.np = bt->gnp[k];
-        P.cp = std::min(bt->cp, P.np);
+        // at most cp planes per chunk, the problem's planes spread evenly
+        // over its chunks (no short last chunk paying a full prologue)
+        P.chunks = (P.np + std::min(bt->cp, P.np) - 1) / std::min(bt->cp, P.np);
+        P.cp = (P.np + P.chunks - 1) / P.chunks;
         P.tiles_x = (P.nx + t.tx - 1) / t.tx;
         P.tiles_y = (P.ny + t.ty - 1) / t.ty;
-        P.chunks = (P.np + P.cp - 1) / P.cp;
         P.item0 = items;
         items += P.tiles_x * P.tiles_y * P.chunks;
         h[k] = P;

@@ -36,7 +36,8 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 CASES = [("d3q19_256_fp32_force", 1e-6), ("d3q19_256_fp64_force", 1e-13),
-         ("d2q9_1024_fp64_eq", 1e-13), ("d2q9_1024_fp32_force", 1e-6)]
+         ("d2q9_1024_fp64_eq", 1e-13), ("d2q9_1024_fp64_force", 1e-13),
+         ("d2q9_1024_fp32_eq", 1e-6), ("d2q9_1024_fp32_force", 1e-6)]
 
 
 def _sites(shape, tile, planes, seed, nrand=1500):
@@ -147,4 +148,45 @@ def test_benchmark_workload_keeps_its_invariants_over_5000_steps():
           % (m0, m1, dm, dm / m0, float(np.max(np.abs(j0))), float(np.max(np.abs(j1))), bound,
              v0, vmax), flush=True)
     assert np.max(np.abs(j0)) <= 1e-9 * m0
+    assert dm <= bound and dj <= bound
+
+
+@pytest.mark.parametrize("wl", ["d2q9_1024_fp64_eq", "d2q9_1024_fp64_force", "d2q9_1024_fp32_eq",
+                                "d2q9_1024_fp32_force"])
+def test_multi_drop_workloads_keep_their_invariants_over_10000_steps(wl):
+    """The 1024^2 D2Q9 workloads (64 drops, both schemes, FP64 and FP32
+    storage) for 10,000 steps in their autotuned launch: the state stays
+    finite, max|v| stays small, and mass and momentum keep their values to
+    rounding: FP64 storage within 1e-12 of the mass (every step conserves
+    both exactly in exact arithmetic), FP32 storage within the rounding bound
+    of the 5000-step test above, 4 * steps * EPS32 * sum_r sum_i |delta_i|."""
+    import bench
+    from paper_0710_5470_amd import autotune, lbm
+    print("[gpu-case] 10000-step invariants", wl, flush=True)
+    q, scheme, storage, compute, shape, T, kappa, tau, R, noise = bench.WORKLOADS[wl]
+    p, rho0 = bench.make_workload(wl)
+    sim = lbm.Simulation(p, rho0)
+    autotune.autotune(sim, use_cache=False)
+    print("[gpu-case] launch", sim.launch(), flush=True)
+    shift = torch.tensor(sim.shift(), dtype=torch.float64, device="cuda")
+
+    def abs_dev():
+        f = sim.get_state()
+        return float((f - shift[:, None]).abs().sum())
+
+    m0, j0 = sim.invariants()
+    d0 = abs_dev()
+    steps = 10000
+    for k in range(4):
+        sim.step(steps // 4)
+        vmax = sim.max_spurious_u()  # raises LBMError on a non-finite state
+        assert vmax < 0.05
+    m1, j1 = sim.invariants()
+    d1 = abs_dev()
+    sim.close()
+    dm = abs(m1 - m0)
+    dj = float(np.max(np.abs(np.array(j1) - np.array(j0))))
+    bound = 1e-12 * m0 if storage == 0 else 4.0 * steps * EPS32 * max(d0, d1)
+    print("[gpu-case] %s: mass drift %.3e (relative %.2e), momentum drift %.3e, bound %.3e, "
+          "max|v| %.3e" % (wl, dm, dm / m0, dj, bound, vmax), flush=True)
     assert dm <= bound and dj <= bound
