@@ -33,6 +33,9 @@ namespace lbm {
 #endif
 // D2Q9 keeps the register march (short marches, see lbm_step.h): 1024^2 FP32
 // forcing 0.0196 against 0.0243 ms per step.
+#ifndef LBM_FORCE_RING64
+#define LBM_FORCE_RING64 1
+#endif
 #ifndef LBM_FORCE_DMA_2D
 #define LBM_FORCE_DMA_2D 0
 #endif
@@ -62,10 +65,18 @@ __device__ __forceinline__ void force_tile(const Job<R> &J, const Coefs<R> &c)
     // lc + 3 is taken into registers (see below); needs every halo site in
     // one pass of the threads and the staging to fit the LDS.
     constexpr int SPL = Q * NT;                    // floats per staging plane
+    // FP32 arithmetic: the density ring holds FP64 values (the rest
+    // deviation added to the FP32 sum of the moving ones without rounding),
+    // and the stencils take differences to the centre in FP64 before
+    // rounding them: an FP32 ring would round every density at its own
+    // scale (|rho - sum s_i| up to ~3, 1.2e-7) and the Laplacian and
+    // gradients would carry those roundings into the equilibrium and the
+    // force every step
+    using RD = std::conditional_t<sizeof(R) == 4 && LBM_FORCE_RING64, double, R>;
     constexpr bool DMA = LBM_FORCE_DMA && (DIM == 3 || LBM_FORCE_DMA_2D) && sizeof(S) == 4 &&
-                         2 * SPL * 4 + (NR * PL + NTC * GPL) * sizeof(R) <= 160 * 1024;
+                         2 * SPL * 4 + NR * PL * sizeof(RD) + NTC * GPL * sizeof(R) <= 160 * 1024;
 
-    __shared__ R rho_s[NR * PL];
+    __shared__ RD rho_s[NR * PL];
     // T components: 3D xx, yy, zz, xy, xz, yz; 2D xx, xy (T_yy = -T_xx)
     __shared__ R t_s[NTC * GPL];
     __shared__ float stage0[DMA ? SPL : 1], stage1[DMA ? SPL : 1];
@@ -168,11 +179,11 @@ __device__ __forceinline__ void force_tile(const Job<R> &J, const Coefs<R> &c)
         }
     };
     // rho - sum_i s_i: moving populations first, the rest population last
-    auto dens = [&](const S(&f)[Q]) -> R {
+    auto dens = [&](const S(&f)[Q]) -> RD {
         R s = sum0<R>();
 #pragma unroll
         for (int i = 1; i < Q; i++) s += R(f[i]);
-        return s + R(f[0]);
+        return RD(s) + RD(R(f[0]));
     };
     auto plane_offsets = [&](int p, int(&P)[3]) {
         P[0] = wrap1(p - 1, np) * psz;
@@ -195,11 +206,11 @@ __device__ __forceinline__ void force_tile(const Job<R> &J, const Coefs<R> &c)
                 pull(hX[s], hY[s], P, hr[s]);
         }
     };
-    auto rho_at = [&](int lp, int lx, int ly) -> R & {
+    auto rho_at = [&](int lp, int lx, int ly) -> RD & {
         return rho_s[(unsigned(lp) % NR) * PL + ly * TXH + lx];
     };
     auto store_rho = [&](int lp, const S(&f)[Q]) {
-        R *ring = rho_s + (unsigned(lp) % NR) * PL;
+        RD *ring = rho_s + (unsigned(lp) % NR) * PL;
         ring[(ty + HY) * TXH + tx + H] = dens(f);
 #pragma unroll
         for (int s = 0; s < NHT; s++)
@@ -235,9 +246,11 @@ __device__ __forceinline__ void force_tile(const Job<R> &J, const Coefs<R> &c)
     // per weight class (Eq. (xderiv); 3D: the A, B stencil)
     auto gradient = [&](int lp, int rx, int ry, R(&d)[3]) {
         R sa[3] = {sum0<R>(), sum0<R>(), sum0<R>()}, so[3] = {sum0<R>(), sum0<R>(), sum0<R>()};
+        // the stencil's weights sum to zero, so the centre may be subtracted
+        const RD rc = rho_at(lp, rx, ry);
 #pragma unroll
         for (int i = 1; i < Q; i++) {
-            const R r = rho_at(lp + op<L>(i), rx + ox<L>(i), ry + oy<L>(i));
+            const R r = R(rho_at(lp + op<L>(i), rx + ox<L>(i), ry + oy<L>(i)) - rc);
             R *acc = nnz<L>(i) == 1 ? sa : so;
             if (L::ex[i]) acc[0] += R(L::ex[i]) * r;
             if (L::ey[i]) acc[1] += R(L::ey[i]) * r;
@@ -267,17 +280,17 @@ __device__ __forceinline__ void force_tile(const Job<R> &J, const Coefs<R> &c)
     auto fill_t = [&](int lp, R(&d_own)[3], R &lap_own) {
         {
             const int rx = tx + H, ry = ty + HY;
-            const R rc = rho_at(lp, rx, ry);
+            const RD rc = rho_at(lp, rx, ry);
             R sa[3] = {sum0<R>(), sum0<R>(), sum0<R>()}, so[3] = {sum0<R>(), sum0<R>(), sum0<R>()};
             R la = sum0<R>();
 #pragma unroll
             for (int i = 1; i < Q; i++) {
-                const R r = rho_at(lp + op<L>(i), rx + ox<L>(i), ry + oy<L>(i));
+                const R r = R(rho_at(lp + op<L>(i), rx + ox<L>(i), ry + oy<L>(i)) - rc);
                 R *acc = nnz<L>(i) == 1 ? sa : so;
                 if (L::ex[i]) acc[0] += R(L::ex[i]) * r;
                 if (L::ey[i]) acc[1] += R(L::ey[i]) * r;
                 if (L::ez[i]) acc[2] += R(L::ez[i]) * r;
-                la += coef_lap<L>(c, i) * (r - rc);
+                la += coef_lap<L>(c, i) * r;
             }
 #pragma unroll
             for (int a = 0; a < 3; a++) d_own[a] = a < DIM ? c.A * sa[a] + c.B * so[a] : R(0);
@@ -402,7 +415,8 @@ __device__ __forceinline__ void force_tile(const Job<R> &J, const Coefs<R> &c)
         // (memory counters retire in order)
         if (DMA && more) take_front(lc + H + 1, SbTake{}, fn);
 
-        const R rho_dev = rho_at(lc, tx + H, ty + HY);
+        const RD rho_dd = rho_at(lc, tx + H, ty + HY);
+        const R rho_dev = R(rho_dd);
         R j[3] = {sum0<R>(), sum0<R>(), DIM == 3 ? sum0<R>() : R(0)};
 #pragma unroll
         for (int i = 1; i < Q; i++) {
@@ -427,7 +441,7 @@ __device__ __forceinline__ void force_tile(const Job<R> &J, const Coefs<R> &c)
                 buf_store(rd, site * ES, unsigned(i * stride) * ES, S(v));
         });
         if (own && J.observe) {
-            J.obs_rho[site] = double(rho_dev) + c.shift_sum;
+            J.obs_rho[site] = double(rho_dd) + c.shift_sum;
             const R h = R(0.5) / es.rho;
             J.obs_vel[site] = double(es.u[0] + h * g[0]);
             J.obs_vel[J.obs_stride + site] = double(es.u[1] + h * g[1]);

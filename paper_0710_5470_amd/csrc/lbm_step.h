@@ -63,6 +63,9 @@ __device__ __forceinline__ double buf_load(__amdgpu_buffer_rsrc_t r, unsigned vo
 // so the stores stream past the caches instead of evicting the neighbour
 // populations that halo loads re-read (the stored state is read again only
 // in the next step, long after it has left the caches).
+#ifndef LBM_EQ_RING64
+#define LBM_EQ_RING64 1
+#endif
 #ifndef LBM_STORE_CPOL
 #define LBM_STORE_CPOL 2
 #endif
@@ -140,7 +143,11 @@ __device__ __forceinline__ void eq_tile(const Job<R> &J, const Coefs<R> &c)
     constexpr int NHT = (NHALO + NT - 1) / NT;  // halo sites per thread
     constexpr unsigned ES = sizeof(S);
 
-    __shared__ R rho_s[NR * PL];
+    // FP32 arithmetic: densities in the ring as FP64 (the FP32 sum of the
+    // moving deviations plus the rest one, not rounded at the scale of
+    // rho - sum s_i), stencils on differences to the centre taken in FP64
+    using RD = std::conditional_t<sizeof(R) == 4 && LBM_EQ_RING64, double, R>;
+    __shared__ RD rho_s[NR * PL];
 
     const S *src = static_cast<const S *>(J.src);
     S *dst = static_cast<S *>(J.dst);
@@ -221,11 +228,11 @@ __device__ __forceinline__ void eq_tile(const Job<R> &J, const Coefs<R> &c)
     // up to ~2, against ~1e-2 for the others), so adding it last leaves one
     // rounding at its scale instead of one per term (the velocity error
     // against the FP64 oracle drops about threefold, at no cost).
-    auto dens = [&](const R(&f)[Q]) -> R {
+    auto dens = [&](const R(&f)[Q]) -> RD {
         R s = sum0<R>();
 #pragma unroll
         for (int i = 1; i < Q; i++) s += f[i];
-        return s + f[0];
+        return RD(s) + RD(f[0]);
     };
 
     auto plane_offsets = [&](int p, int(&P)[3]) {
@@ -234,7 +241,7 @@ __device__ __forceinline__ void eq_tile(const Job<R> &J, const Coefs<R> &c)
         P[2] = wrap1(p + 1, np) * psz;
     };
 
-    auto rho_at = [&](int lp, int lx, int ly) -> R & {
+    auto rho_at = [&](int lp, int lx, int ly) -> RD & {
         return rho_s[(unsigned(lp) % NR) * PL + ly * TXH + lx];
     };
 
@@ -254,7 +261,7 @@ __device__ __forceinline__ void eq_tile(const Job<R> &J, const Coefs<R> &c)
             if (hv[s]) pull(hX[s], hY[s], P, hr[s]);
     };
     auto store_rho = [&](int lp, const R(&f)[Q]) {
-        R *ring = rho_s + (unsigned(lp) % NR) * PL;
+        RD *ring = rho_s + (unsigned(lp) % NR) * PL;
         ring[(ty + HY) * TXH + tx + H] = dens(f);
 #pragma unroll
         for (int s = 0; s < NHT; s++)
@@ -299,7 +306,8 @@ __device__ __forceinline__ void eq_tile(const Job<R> &J, const Coefs<R> &c)
         }
         __syncthreads();  // densities up to plane lc + H are in LDS
         const int lx = tx + H, ly = ty + HY;
-        const R rho_dev = rho_at(lc, lx, ly);
+        const RD rho_dd = rho_at(lc, lx, ly);
+        const R rho_dev = R(rho_dd);
         R j[3] = {sum0<R>(), sum0<R>(), L::DIM == 3 ? sum0<R>() : R(0)};
 #pragma unroll
         for (int i = 1; i < Q; i++) {
@@ -313,12 +321,13 @@ __device__ __forceinline__ void eq_tile(const Job<R> &J, const Coefs<R> &c)
         R lap = sum0<R>();
 #pragma unroll
         for (int i = 1; i < Q; i++) {
-            const R r = rho_at(lc + op<L>(i), lx + ox<L>(i), ly + oy<L>(i));
+            // (the stencil weights sum to zero: differences to the centre)
+            const R r = R(rho_at(lc + op<L>(i), lx + ox<L>(i), ly + oy<L>(i)) - rho_dd);
             R *acc = nnz<L>(i) == 1 ? sa : so;
             if (L::ex[i]) acc[0] += R(L::ex[i]) * r;
             if (L::ey[i]) acc[1] += R(L::ey[i]) * r;
             if (L::ez[i]) acc[2] += R(L::ez[i]) * r;
-            lap += coef_lap<L>(c, i) * (r - rho_dev);
+            lap += coef_lap<L>(c, i) * r;
         }
         R d[3];
 #pragma unroll
@@ -331,7 +340,7 @@ __device__ __forceinline__ void eq_tile(const Job<R> &J, const Coefs<R> &c)
         const EqSite<R> es =
             collide<L, false>(c, rho_dev, j, d, lap, g, fr[C0], [&](int i, R v) { out[i] = v; });
         if (own && J.observe) {
-            J.obs_rho[site] = double(rho_dev) + c.shift_sum;
+            J.obs_rho[site] = double(rho_dd) + c.shift_sum;
             J.obs_vel[site] = double(es.u[0]);
             J.obs_vel[J.obs_stride + site] = double(es.u[1]);
             J.obs_vel[2 * J.obs_stride + site] = double(L::DIM == 3 ? es.u[2] : R(0));
@@ -399,7 +408,11 @@ __device__ __forceinline__ void eq_tile_dma(const Job<R> &J, const Coefs<R> &c)
     constexpr int SPL = Q * NT;                 // floats per staging plane
     constexpr unsigned OOR = 0xFFFFFFFFu - (ES - 1);
 
-    __shared__ R rho_s[NR * PL];
+    // FP32 arithmetic: densities in the ring as FP64 (the FP32 sum of the
+    // moving deviations plus the rest one, not rounded at the scale of
+    // rho - sum s_i), stencils on differences to the centre taken in FP64
+    using RD = std::conditional_t<sizeof(R) == 4 && LBM_EQ_RING64, double, R>;
+    __shared__ RD rho_s[NR * PL];
     __shared__ float stage0[SPL], stage1[SPL];
 
     const S *src = static_cast<const S *>(J.src);
@@ -469,18 +482,18 @@ __device__ __forceinline__ void eq_tile_dma(const Job<R> &J, const Coefs<R> &c)
             f[i] = buf_load(rs, (e * ES) | oor, unsigned(i * stride) * ES, S());
         }
     };
-    auto dens = [&](const S(&f)[Q]) -> R {
+    auto dens = [&](const S(&f)[Q]) -> RD {
         R s = sum0<R>();
 #pragma unroll
         for (int i = 1; i < Q; i++) s += R(f[i]);
-        return s + R(f[0]);
+        return RD(s) + RD(R(f[0]));
     };
     auto plane_offsets = [&](int p, int(&P)[3]) {
         P[0] = wrap1(p - 1, np) * psz;
         P[1] = p * psz;
         P[2] = wrap1(p + 1, np) * psz;
     };
-    auto rho_at = [&](int lp, int lx, int ly) -> R & {
+    auto rho_at = [&](int lp, int lx, int ly) -> RD & {
         return rho_s[(unsigned(lp) % NR) * PL + ly * TXH + lx];
     };
     auto load_own = [&](int pg, S(&f)[Q]) {
@@ -495,7 +508,7 @@ __device__ __forceinline__ void eq_tile_dma(const Job<R> &J, const Coefs<R> &c)
         for (int s = 0; s < NHT; s++) pull(hX[s], hY[s], P, hr[s], valid && hv[s]);
     };
     auto store_rho = [&](int lp, const S(&f)[Q]) {
-        R *ring = rho_s + (unsigned(lp) % NR) * PL;
+        RD *ring = rho_s + (unsigned(lp) % NR) * PL;
         ring[(ty + HY) * TXH + tx + H] = dens(f);
 #pragma unroll
         for (int s = 0; s < NHT; s++)
@@ -553,7 +566,8 @@ __device__ __forceinline__ void eq_tile_dma(const Job<R> &J, const Coefs<R> &c)
         // own populations of plane lc + 3, taken in the next iteration
         dma_front(pg_f2, SbIssue{}, k + 2 < npl);
         const int lx = tx + H, ly = ty + HY;
-        const R rho_dev = rho_at(lc, lx, ly);
+        const RD rho_dd = rho_at(lc, lx, ly);
+        const R rho_dev = R(rho_dd);
         S(&fc)[Q] = fr[C0];
         R j[3] = {sum0<R>(), sum0<R>(), L::DIM == 3 ? sum0<R>() : R(0)};
 #pragma unroll
@@ -566,12 +580,13 @@ __device__ __forceinline__ void eq_tile_dma(const Job<R> &J, const Coefs<R> &c)
         R lap = sum0<R>();
 #pragma unroll
         for (int i = 1; i < Q; i++) {
-            const R r = rho_at(lc + op<L>(i), lx + ox<L>(i), ly + oy<L>(i));
+            // (the stencil weights sum to zero: differences to the centre)
+            const R r = R(rho_at(lc + op<L>(i), lx + ox<L>(i), ly + oy<L>(i)) - rho_dd);
             R *acc = nnz<L>(i) == 1 ? sa : so;
             if (L::ex[i]) acc[0] += R(L::ex[i]) * r;
             if (L::ey[i]) acc[1] += R(L::ey[i]) * r;
             if (L::ez[i]) acc[2] += R(L::ez[i]) * r;
-            lap += coef_lap<L>(c, i) * (r - rho_dev);
+            lap += coef_lap<L>(c, i) * r;
         }
         R d[3];
 #pragma unroll
@@ -583,7 +598,7 @@ __device__ __forceinline__ void eq_tile_dma(const Job<R> &J, const Coefs<R> &c)
         for (int i = 0; i < Q; i++) fin[i] = R(fc[i]);
         const EqSite<R> es = collide<L, false>(c, rho_dev, j, d, lap, g, fin, [&](int i, R v) { out[i] = v; });
         if (own && J.observe) {
-            J.obs_rho[site] = double(rho_dev) + c.shift_sum;
+            J.obs_rho[site] = double(rho_dd) + c.shift_sum;
             J.obs_vel[site] = double(es.u[0]);
             J.obs_vel[J.obs_stride + site] = double(es.u[1]);
             J.obs_vel[2 * J.obs_stride + site] = double(L::DIM == 3 ? es.u[2] : R(0));
@@ -632,9 +647,10 @@ template <class L, int SCHEME, class S, class R, int TX, int TY>
 __device__ __forceinline__ void tile_step(const Job<R> &J, const Coefs<R> &c)
 {
     constexpr int NT = TX * TY, Q = L::Q, PLE = (TX + 2) * (TY + (L::DIM == 3 ? 2 : 0));
+    constexpr int RDS = sizeof(R) == 4 && LBM_EQ_RING64 ? 8 : int(sizeof(R));  // ring element
     constexpr bool EQ_DMA =
         LBM_EQ_DMA && (L::DIM == 3 || LBM_EQ_DMA_2D) && sizeof(S) == 4 &&
-        (2 * Q * NT * 4 + 4 * PLE * int(sizeof(R))) <= 160 * 1024;
+        (2 * Q * NT * 4 + 4 * PLE * RDS) <= 160 * 1024;
     if constexpr (SCHEME == SCHEME_FORCE)
         force_tile<L, S, R, TX, TY>(J, c);
     else if constexpr (EQ_DMA)
