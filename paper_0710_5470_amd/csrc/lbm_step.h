@@ -82,8 +82,12 @@ __device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, unsigned vof
                                           r, (int)voff, (int)soff, LBM_STORE_CPOL);
 }
 
+// Minimum waves per SIMD the step kernel is compiled for; 0 = per
+// instance: four for the D2Q9 FP32 forcing kernel (its FP64 density ring
+// takes it to 135 VGPRs, three waves; capped at 128 it keeps four, which
+// this small, cache-resident kernel needs), the compiler's choice elsewhere.
 #ifndef LBM_STEP_WAVES_PER_EU
-#define LBM_STEP_WAVES_PER_EU 1
+#define LBM_STEP_WAVES_PER_EU 0
 #endif
 // The same for the batched (persistent) kernel; 0 = per instance: three
 // waves per SIMD for the D2Q9 FP64 equilibrium kernel (172 -> 168 VGPRs,
@@ -92,6 +96,11 @@ __device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, unsigned vof
 #ifndef LBM_BATCH_WAVES_PER_EU
 #define LBM_BATCH_WAVES_PER_EU 0
 #endif
+template <class L, int SCHEME, class S, class R> constexpr int step_waves_per_eu()
+{
+    if (LBM_STEP_WAVES_PER_EU > 0) return LBM_STEP_WAVES_PER_EU;
+    return (L::DIM == 2 && SCHEME == SCHEME_FORCE && sizeof(S) == 4 && sizeof(R) == 4) ? 4 : 1;
+}
 template <class L, int SCHEME, class S> constexpr int batch_waves_per_eu()
 {
     if (LBM_BATCH_WAVES_PER_EU > 0) return LBM_BATCH_WAVES_PER_EU;
@@ -661,7 +670,7 @@ __device__ __forceinline__ void tile_step(const Job<R> &J, const Coefs<R> &c)
 
 // One problem: workgroup b takes tile (b mod tiles_x, ...) of chunk b / tiles.
 template <class L, int SCHEME, class S, class R, int TX, int TY>
-__global__ __launch_bounds__(TX *TY) __attribute__((amdgpu_waves_per_eu(LBM_STEP_WAVES_PER_EU)))
+__global__ __launch_bounds__(TX *TY) __attribute__((amdgpu_waves_per_eu(step_waves_per_eu<L, SCHEME, S, R>())))
 void step_kernel(StepArgs<R> A)
 {
     // XCD-aware order: consecutive workgroup ids go to different XCDs, so
