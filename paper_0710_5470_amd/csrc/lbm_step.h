@@ -59,13 +59,15 @@ __device__ __forceinline__ double buf_load(__amdgpu_buffer_rsrc_t r, unsigned vo
 {
     return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
 }
+// FP32 arithmetic in the equilibrium marches with an FP64 density ring (see
+// the ring in eq_tile)
+#ifndef LBM_EQ_RING64
+#define LBM_EQ_RING64 1
+#endif
 // Cache policy of the population stores: 2 sets the non-temporal bit (nt),
 // so the stores stream past the caches instead of evicting the neighbour
 // populations that halo loads re-read (the stored state is read again only
 // in the next step, long after it has left the caches).
-#ifndef LBM_EQ_RING64
-#define LBM_EQ_RING64 1
-#endif
 #ifndef LBM_STORE_CPOL
 #define LBM_STORE_CPOL 2
 #endif
