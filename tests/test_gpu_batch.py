@@ -33,7 +33,7 @@ SPECS = [dict(side=37, ny=29, radius=8.0, T=0.55, kappa=0.01, tau=0.9),
          dict(side=32, radius=6.0, T=0.55, kappa=0.015)]
 
 
-@pytest.mark.parametrize("scheme,storage", [(0, 0), (1, 0), (1, 1)])
+@pytest.mark.parametrize("scheme,storage", [(0, 0), (1, 0), (1, 1), (0, 1)])
 def test_batch_steps_match_single_problem_runs(scheme, storage):
     from paper_0710_5470_amd import lbm
     plist, rho = _problems(SPECS, scheme, storage)
@@ -52,11 +52,12 @@ def test_batch_steps_match_single_problem_runs(scheme, storage):
         assert np.array_equal(v, vb[k]), k
 
 
-def test_batch_graph_replays_match_eager_steps():
+@pytest.mark.parametrize("scheme,storage", [(1, 0), (0, 1)])
+def test_batch_graph_replays_match_eager_steps(scheme, storage):
     """Each graph replay runs K steps plus the check; replays must leave the
     same state as the same number of eagerly launched steps."""
     from paper_0710_5470_amd import lbm
-    plist, rho = _problems(SPECS, 1, 0)
+    plist, rho = _problems(SPECS, scheme, storage)
     a = lbm.Batch(plist, rho)
     steps, res, status = a.run(tol=0.0, check_every=10, max_steps=50)
     assert all(s == lbm.BATCH_MAXSTEPS for s in status)
