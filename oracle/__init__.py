@@ -200,3 +200,105 @@ def set_threads(n):
 
 def max_threads():
     return int(lib().orc_max_threads())
+
+
+# ---- binary fluid ------------------------------------------------------------
+
+class OrcBinParams(ctypes.Structure):
+    _fields_ = [("base", OrcParams), ("phi_a", ctypes.c_double), ("phi_b", ctypes.c_double),
+                ("gamma", ctypes.c_double), ("tau_phi", ctypes.c_double)]
+
+
+def bin_params(q=9, shape=(64, 64), phi_a=-0.02, phi_b=0.02, kappa=0.04, tau=1.0,
+               tau_phi=1.0, gamma=1.0, **over):
+    """Symmetric binary fluid: bulk free energy phi_a phi^2/2 + phi_b phi^4/4
+    plus kappa |grad phi|^2 / 2, ideal-gas carrier rho/3."""
+    base = params(q=q, scheme=0, shape=shape, a=0.0, b=0.0, T=0.0, kappa=kappa, tau=tau,
+                  lambda_on=0, **over)
+    return OrcBinParams(base, phi_a, phi_b, gamma, tau_phi)
+
+
+def _bin_lib():
+    L = lib()
+    if not getattr(L, "_bin_ready", False):
+        dp = ctypes.POINTER(ctypes.c_double)
+        bp = ctypes.POINTER(OrcBinParams)
+        L.orc_bin_init.argtypes = [bp, dp, dp, dp, dp, dp]
+        L.orc_bin_init.restype = ctypes.c_int
+        L.orc_bin_run.argtypes = [bp, dp, dp, ctypes.c_int]
+        L.orc_bin_run.restype = ctypes.c_int
+        L.orc_bin_observe.argtypes = [bp, dp, dp, dp, dp, dp, dp]
+        L.orc_bin_observe.restype = ctypes.c_int
+        L.orc_bin_totals.argtypes = [bp, dp, dp, dp, dp, dp]
+        L.orc_bin_totals.restype = ctypes.c_int
+        L.orc_bin_feq_site.argtypes = [bp, ctypes.c_double, dp, ctypes.c_double, dp,
+                                       ctypes.c_double, dp]
+        L.orc_bin_geq_site.argtypes = [bp, ctypes.c_double, dp, ctypes.c_double, dp]
+        L._bin_ready = True
+    return L
+
+
+def _bn(bp):
+    return bp.base.nx * bp.base.ny * bp.base.nz
+
+
+def bin_init(bp, rho0, phi0, u0=None):
+    """(f, g) [q][n] at the binary equilibria of rho0, phi0, u0."""
+    n = _bn(bp)
+    rho0 = np.ascontiguousarray(rho0, dtype=np.float64).reshape(-1)
+    phi0 = np.ascontiguousarray(phi0, dtype=np.float64).reshape(-1)
+    assert rho0.size == n and phi0.size == n
+    f = np.empty((bp.base.q, n))
+    g = np.empty((bp.base.q, n))
+    u = None if u0 is None else np.ascontiguousarray(u0, dtype=np.float64).reshape(3, n)
+    rc = _bin_lib().orc_bin_init(ctypes.byref(bp), _p(rho0), _p(phi0),
+                                 None if u is None else _p(u), _p(f), _p(g))
+    if rc != 0:
+        raise ValueError("oracle rejected the parameters")
+    return f, g
+
+
+def bin_run(bp, f, g, nsteps):
+    """Advance copies of (f, g) by nsteps."""
+    f = np.ascontiguousarray(f, dtype=np.float64).copy()
+    g = np.ascontiguousarray(g, dtype=np.float64).copy()
+    if _bin_lib().orc_bin_run(ctypes.byref(bp), _p(f), _p(g), int(nsteps)) != 0:
+        raise ValueError("oracle rejected the parameters")
+    return f, g
+
+
+def bin_observe(bp, f, g):
+    """(rho[n], phi[n], u[3][n], mu[n])."""
+    n = _bn(bp)
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    g = np.ascontiguousarray(g, dtype=np.float64)
+    rho, phi, vel, mu = np.empty(n), np.empty(n), np.empty((3, n)), np.empty(n)
+    _bin_lib().orc_bin_observe(ctypes.byref(bp), _p(f), _p(g), _p(rho), _p(phi), _p(vel), _p(mu))
+    return rho, phi, vel, mu
+
+
+def bin_totals(bp, f, g):
+    """(mass, sum phi, momentum[3])."""
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    g = np.ascontiguousarray(g, dtype=np.float64)
+    m, ph = ctypes.c_double(), ctypes.c_double()
+    mom = np.empty(3)
+    _bin_lib().orc_bin_totals(ctypes.byref(bp), _p(f), _p(g), ctypes.byref(m), ctypes.byref(ph),
+                              _p(mom))
+    return m.value, ph.value, mom
+
+
+def bin_feq_site(bp, rho, j, phi, grad, lap):
+    out = np.empty(bp.base.q)
+    j = np.ascontiguousarray(j, dtype=np.float64)
+    grad = np.ascontiguousarray(grad, dtype=np.float64)
+    _bin_lib().orc_bin_feq_site(ctypes.byref(bp), float(rho), _p(j), float(phi), _p(grad),
+                                float(lap), _p(out))
+    return out
+
+
+def bin_geq_site(bp, phi, u, lap):
+    out = np.empty(bp.base.q)
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    _bin_lib().orc_bin_geq_site(ctypes.byref(bp), float(phi), _p(u), float(lap), _p(out))
+    return out

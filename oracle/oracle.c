@@ -699,3 +699,259 @@ int orc_max_threads(void)
     return 1;
 #endif
 }
+
+/* ==== binary fluid (order parameter phi) ====================================
+ *
+ * The Introduction states that the analysis carries over to other multiphase
+ * systems such as binary fluids, without giving that model.  This section
+ * takes the symmetric binary free energy
+ *     Psi = sum_r [ rho/3 + phi_a phi^2/2 + phi_b phi^4/4 + kappa |d phi|^2/2 ]
+ * (an ideal-gas carrier rho with c_s^2 = 1/3, a double-well bulk term in the
+ * order parameter phi, phi_a < 0 < phi_b) and applies the paper's tuned
+ * equilibrium to it, with phi in the place of rho wherever rho is
+ * differentiated:
+ *   - f equilibrium: Eq. (equilibrium)/(feq0) with bulk pressure
+ *     p0 = rho/3 + phi psi'(phi) - psi(phi) = rho/3 + phi_a phi^2/2
+ *     + 3 phi_b phi^4/4, the w^t term -w^t_i kappa phi lap(phi), the w^ab
+ *     terms kappa d_a phi d_b phi, and no lambda term (lambda = nu (1 - 3
+ *     c_s^2) vanishes for c_s^2 = 1/3, Eq. (viscous));
+ *   - a second distribution g_i relaxing (time tau_phi) to an equilibrium
+ *     with moments sum g = phi, sum g e_a = phi u_a and sum g e_a e_b =
+ *     gamma mu delta_ab + phi u_a u_b, mu = phi_a phi + phi_b phi^3 -
+ *     kappa lap(phi); the gamma mu term is carried by the pressure weights
+ *     w^p_i (the role p0 plays in the f equilibrium), the velocity terms by
+ *     w_i, and g_0 closes the zeroth moment;
+ *   - gradients and Laplacians with the same stencils as the liquid-gas
+ *     model (Eqs. (xderiv), (laplace), (laplacian3d)).
+ * Only the tuned-equilibrium scheme is defined for the binary fluid.
+ */
+typedef struct {
+    orc_params base;     /* q, extent, kappa, tau, stencils, weights */
+    double phi_a, phi_b; /* bulk free energy phi_a phi^2/2 + phi_b phi^4/4 */
+    double gamma;        /* mobility coefficient of the mu term */
+    double tau_phi;      /* relaxation time of g */
+} orc_bin_params;
+
+static double bin_p0(const orc_bin_params *bp, double rho, double phi)
+{
+    double p2 = phi * phi;
+    return rho / 3.0 + 0.5 * bp->phi_a * p2 + 0.75 * bp->phi_b * p2 * p2;
+}
+
+static double bin_mu(const orc_bin_params *bp, double phi, double lap)
+{
+    return bp->phi_a * phi + bp->phi_b * phi * phi * phi - bp->base.kappa * lap;
+}
+
+/* f equilibrium of the binary fluid at one site: grad, lap of phi */
+static void feq_bin_site_t(const orc_bin_params *bp, const tables *t, double rho,
+                           const double j[3], double phi, const double grad[3], double lap,
+                           double *feq)
+{
+    const double kappa = bp->base.kappa;
+    int dim = t->dim;
+    double u[3] = {j[0] / rho, j[1] / rho, j[2] / rho};
+    double p0 = bin_p0(bp, rho, phi);
+    double M[6] = {kappa * grad[0] * grad[0], kappa * grad[1] * grad[1],
+                   kappa * grad[2] * grad[2], kappa * grad[0] * grad[1],
+                   kappa * grad[1] * grad[2], kappa * grad[2] * grad[0]};
+    double sum = 0.0;
+    for (int i = 1; i < t->q; i++) {
+        const int *e = t->e[i];
+        double ej = 0.0, ex = 0.0;
+        for (int al = 0; al < dim; al++) ej += e[al] * j[al];
+        for (int al = 0; al < dim; al++)
+            for (int be = 0; be < dim; be++)
+                ex += (e[al] * e[be] - (al == be ? 1.0 / 3.0 : 0.0)) * rho * u[al] * u[be];
+        double v = t->w[i] * (ej + 1.5 * ex) + t->wp[i] * p0 - t->wt[i] * kappa * phi * lap;
+        for (int m = 0; m < 6; m++) v += t->wm[m][i] * M[m];
+        feq[i] = v;
+        sum += v;
+    }
+    feq[0] = rho - sum;
+}
+
+/* g equilibrium at one site */
+static void geq_bin_site_t(const orc_bin_params *bp, const tables *t, double phi,
+                           const double u[3], double mu, double *geq)
+{
+    int dim = t->dim;
+    double sum = 0.0;
+    for (int i = 1; i < t->q; i++) {
+        const int *e = t->e[i];
+        double eu = 0.0, ex = 0.0;
+        for (int al = 0; al < dim; al++) eu += e[al] * u[al];
+        for (int al = 0; al < dim; al++)
+            for (int be = 0; be < dim; be++)
+                ex += (e[al] * e[be] - (al == be ? 1.0 / 3.0 : 0.0)) * u[al] * u[be];
+        double v = t->wp[i] * bp->gamma * mu + t->w[i] * phi * (eu + 1.5 * ex);
+        geq[i] = v;
+        sum += v;
+    }
+    geq[0] = phi - sum;
+}
+
+static int bin_valid(const orc_bin_params *bp)
+{
+    const orc_params *p = &bp->base;
+    if (!(p->q == 9 || p->q == 19)) return 0;
+    if (p->q == 9 && p->nz != 1) return 0;
+    return p->nx > 0 && p->ny > 0 && p->nz > 0;
+}
+
+/* phi = sum_i g_i */
+static void order_parameter(const orc_params *p, const tables *t, const double *g, double *phi)
+{
+    long n = nsites(p);
+#pragma omp parallel for schedule(static)
+    for (long s = 0; s < n; s++) {
+        double v = 0.0;
+        for (int i = 0; i < t->q; i++) v += g[i * n + s];
+        phi[s] = v;
+    }
+}
+
+/* Initial populations: f = f^eq(rho0, rho0 u0, phi0), g = g^eq(phi0, u0, mu). */
+int orc_bin_init(const orc_bin_params *bp, const double *rho0, const double *phi0,
+                 const double *u0, double *f, double *g)
+{
+    if (!bin_valid(bp)) return -1;
+    const orc_params *p = &bp->base;
+    tables t;
+    build_tables(p, &t);
+    long n = nsites(p);
+    double *grad = (double *)malloc(sizeof(double) * 3 * n);
+    double *lap = (double *)malloc(sizeof(double) * n);
+    derivatives(p, &t, phi0, grad, lap);
+#pragma omp parallel for schedule(static)
+    for (long s = 0; s < n; s++) {
+        double u[3] = {0, 0, 0}, j[3];
+        if (u0)
+            for (int a = 0; a < 3; a++) u[a] = u0[a * n + s];
+        for (int a = 0; a < 3; a++) j[a] = rho0[s] * u[a];
+        double d[3] = {grad[s], grad[n + s], grad[2 * n + s]};
+        double fe[19], ge[19];
+        feq_bin_site_t(bp, &t, rho0[s], j, phi0[s], d, lap[s], fe);
+        geq_bin_site_t(bp, &t, phi0[s], u, bin_mu(bp, phi0[s], lap[s]), ge);
+        for (int i = 0; i < t.q; i++) {
+            f[i * n + s] = fe[i];
+            g[i * n + s] = ge[i];
+        }
+    }
+    free(grad);
+    free(lap);
+    return 0;
+}
+
+/* Advance (f, g) in place by nsteps: both distributions collide (BGK, tau
+ * and tau_phi) and stream as in Eq. (latbolt). */
+int orc_bin_run(const orc_bin_params *bp, double *f, double *g, int nsteps)
+{
+    if (!bin_valid(bp) || nsteps < 0) return -1;
+    const orc_params *p = &bp->base;
+    tables t;
+    build_tables(p, &t);
+    long n = nsites(p);
+    int q = t.q;
+    double *fb = (double *)malloc(sizeof(double) * n * q);
+    double *gb = (double *)malloc(sizeof(double) * n * q);
+    double *rho = (double *)malloc(sizeof(double) * n);
+    double *j = (double *)malloc(sizeof(double) * 3 * n);
+    double *phi = (double *)malloc(sizeof(double) * n);
+    double *grad = (double *)malloc(sizeof(double) * 3 * n);
+    double *lap = (double *)malloc(sizeof(double) * n);
+    double *fc = f, *gc = g, *fn = fb, *gn = gb;
+    for (int step = 0; step < nsteps; step++) {
+        moments(p, &t, fc, rho, j);
+        order_parameter(p, &t, gc, phi);
+        derivatives(p, &t, phi, grad, lap);
+#pragma omp parallel for collapse(2) schedule(static)
+        for (int z = 0; z < p->nz; z++)
+            for (int y = 0; y < p->ny; y++)
+                for (int x = 0; x < p->nx; x++) {
+                    long s = sidx(p, x, y, z);
+                    double jj[3] = {j[s], j[n + s], j[2 * n + s]};
+                    double u[3] = {jj[0] / rho[s], jj[1] / rho[s], jj[2] / rho[s]};
+                    double d[3] = {grad[s], grad[n + s], grad[2 * n + s]};
+                    double fe[19], ge[19];
+                    feq_bin_site_t(bp, &t, rho[s], jj, phi[s], d, lap[s], fe);
+                    geq_bin_site_t(bp, &t, phi[s], u, bin_mu(bp, phi[s], lap[s]), ge);
+                    for (int i = 0; i < q; i++) {
+                        const int *e = t.e[i];
+                        long dst = i * n + sidx(p, x + e[0], y + e[1], z + e[2]);
+                        double fi = fc[i * n + s], gi = gc[i * n + s];
+                        fn[dst] = fi - (fi - fe[i]) / p->tau;
+                        gn[dst] = gi - (gi - ge[i]) / bp->tau_phi;
+                    }
+                }
+        double *tf = fc, *tg = gc;
+        fc = fn; gc = gn; fn = tf; gn = tg;
+    }
+    if (fc != f) {
+        memcpy(f, fc, sizeof(double) * n * q);
+        memcpy(g, gc, sizeof(double) * n * q);
+    }
+    free(fb); free(gb); free(rho); free(j); free(phi); free(grad); free(lap);
+    return 0;
+}
+
+/* Observables: rho [n], phi [n], u = j / rho [3][n], mu [n] (any may be NULL). */
+int orc_bin_observe(const orc_bin_params *bp, const double *f, const double *g, double *rho,
+                    double *phi, double *vel, double *mu)
+{
+    if (!bin_valid(bp)) return -1;
+    const orc_params *p = &bp->base;
+    tables t;
+    build_tables(p, &t);
+    long n = nsites(p);
+    double *r = (double *)malloc(sizeof(double) * n);
+    double *j = (double *)malloc(sizeof(double) * 3 * n);
+    double *ph = (double *)malloc(sizeof(double) * n);
+    double *grad = (double *)malloc(sizeof(double) * 3 * n);
+    double *lap = (double *)malloc(sizeof(double) * n);
+    moments(p, &t, f, r, j);
+    order_parameter(p, &t, g, ph);
+    derivatives(p, &t, ph, grad, lap);
+    for (long s = 0; s < n; s++) {
+        if (rho) rho[s] = r[s];
+        if (phi) phi[s] = ph[s];
+        if (vel)
+            for (int a = 0; a < 3; a++) vel[a * n + s] = j[a * n + s] / r[s];
+        if (mu) mu[s] = bin_mu(bp, ph[s], lap[s]);
+    }
+    free(r); free(j); free(ph); free(grad); free(lap);
+    return 0;
+}
+
+/* Totals (serial, FP64): mass sum f, order parameter sum g, momentum sum f e. */
+int orc_bin_totals(const orc_bin_params *bp, const double *f, const double *g, double *mass,
+                   double *phi_total, double *mom)
+{
+    if (!bin_valid(bp)) return -1;
+    orc_totals(&bp->base, f, mass, mom);
+    const orc_params *p = &bp->base;
+    long n = nsites(p);
+    int q = (p->q == 9) ? 9 : 19;
+    double s = 0.0;
+    for (int i = 0; i < q; i++)
+        for (long k = 0; k < n; k++) s += g[i * n + k];
+    *phi_total = s;
+    return 0;
+}
+
+/* Equilibria at one site for given moments and derivatives of phi. */
+void orc_bin_feq_site(const orc_bin_params *bp, double rho, const double *j, double phi,
+                      const double *grad, double lap, double *feq)
+{
+    tables t;
+    build_tables(&bp->base, &t);
+    feq_bin_site_t(bp, &t, rho, j, phi, grad, lap, feq);
+}
+
+void orc_bin_geq_site(const orc_bin_params *bp, double phi, const double *u, double lap,
+                      double *geq)
+{
+    tables t;
+    build_tables(&bp->base, &t);
+    geq_bin_site_t(bp, &t, phi, u, bin_mu(bp, phi, lap), geq);
+}

@@ -1,0 +1,264 @@
+"""Pins of the oracle's binary-fluid stepper (CPU only).
+
+The paper's Introduction says its analysis carries over to binary fluids
+without giving that model; the oracle takes the symmetric phi^4 free energy
+with an ideal-gas carrier density and the paper's tuned equilibrium with phi
+in the place of the differentiated density.  What fixes it here:
+  - the moments each equilibrium must have: the pressure tensor of the
+    free energy (Appendix A's second-moment condition, written from the
+    free energy's Legendre transform, not from the oracle's weights), and
+    the order-parameter moments phi, phi u, gamma mu delta + phi u u;
+  - at phi = 0 the f equilibrium is the textbook isothermal equilibrium;
+  - mass, order parameter and momentum are conserved;
+  - a flat interface relaxes to the solution of the discrete steady
+    equation psi'(phi) - kappa lap_h(phi) = mu_0 (uniform chemical
+    potential at zero velocity), solved here by Newton's method, and that
+    solution approaches phi_0 tanh(x / xi) at second order in 1 / xi;
+  - the optimum stencils and weights lower the spurious velocities of a
+    drop several-fold against a non-optimum stencil or weight.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+
+PA, PB, KAPPA = -0.02, 0.02, 0.04
+
+
+def _psi(phi):
+    return PA * phi ** 2 / 2 + PB * phi ** 4 / 4
+
+
+def _dpsi(phi):
+    return PA * phi + PB * phi ** 3
+
+
+def _textbook_weight(e):
+    """Isothermal equilibrium weights by speed: D2Q9 4/9, 1/9, 1/36;
+    D3Q19 1/3, 1/18, 1/36."""
+    q = len(e)
+    e2 = (e ** 2).sum(1)
+    if q == 9:
+        return np.where(e2 == 0, 4 / 9, np.where(e2 == 1, 1 / 9, 1 / 36))
+    return np.where(e2 == 0, 1 / 3, np.where(e2 == 1, 1 / 18, 1 / 36))
+
+
+@pytest.mark.parametrize("q", [9, 19])
+def test_binary_feq_moments_are_the_free_energy_pressure_tensor(q):
+    bp = O.bin_params(q=q, shape=(4, 4, 4) if q == 19 else (4, 4), phi_a=PA, phi_b=PB,
+                      kappa=KAPPA)
+    e = O.tables(bp.base)["e"].astype(float)
+    dim = 3 if q == 19 else 2
+    rng = np.random.default_rng(11)
+    for _ in range(20):
+        rho = rng.uniform(0.8, 1.2)
+        phi = rng.uniform(-1.1, 1.1)
+        j = np.zeros(3)
+        j[:dim] = rng.normal(0, 0.05, dim)
+        grad = np.zeros(3)
+        grad[:dim] = rng.normal(0, 0.2, dim)
+        lap = rng.normal(0, 0.1)
+        f = O.bin_feq_site(bp, rho, j, phi, grad, lap)
+        u = j / rho
+        # bulk pressure by the Legendre transform of the free energy density
+        pb = rho / 3 + phi * _dpsi(phi) - _psi(phi)
+        P = (pb - KAPPA * phi * lap - KAPPA / 2 * grad @ grad) * np.eye(3) \
+            + KAPPA * np.outer(grad, grad)
+        want2 = (P + rho * np.outer(u, u))[:dim, :dim]
+        got2 = np.einsum("i,ia,ib->ab", f, e, e)[:dim, :dim]
+        assert abs(f.sum() - rho) < 1e-14
+        np.testing.assert_allclose(f @ e, j, atol=1e-15)
+        np.testing.assert_allclose(got2, want2, atol=1e-14)
+
+
+@pytest.mark.parametrize("q", [9, 19])
+def test_binary_geq_moments(q):
+    gamma = 0.7
+    bp = O.bin_params(q=q, shape=(4, 4, 4) if q == 19 else (4, 4), phi_a=PA, phi_b=PB,
+                      kappa=KAPPA, gamma=gamma)
+    e = O.tables(bp.base)["e"].astype(float)
+    dim = 3 if q == 19 else 2
+    rng = np.random.default_rng(12)
+    for _ in range(20):
+        phi = rng.uniform(-1.1, 1.1)
+        u = np.zeros(3)
+        u[:dim] = rng.normal(0, 0.05, dim)
+        lap = rng.normal(0, 0.1)
+        g = O.bin_geq_site(bp, phi, u, lap)
+        mu = _dpsi(phi) - KAPPA * lap
+        assert abs(g.sum() - phi) < 1e-14
+        np.testing.assert_allclose(g @ e, phi * u, atol=1e-15)
+        want2 = (gamma * mu * np.eye(3) + phi * np.outer(u, u))[:dim, :dim]
+        np.testing.assert_allclose(np.einsum("i,ia,ib->ab", g, e, e)[:dim, :dim], want2,
+                                   atol=1e-15)
+
+
+@pytest.mark.parametrize("q", [9, 19])
+def test_binary_feq_at_zero_phi_is_the_textbook_isothermal_equilibrium(q):
+    bp = O.bin_params(q=q, shape=(4, 4, 4) if q == 19 else (4, 4), phi_a=PA, phi_b=PB,
+                      kappa=KAPPA)
+    e = O.tables(bp.base)["e"].astype(float)
+    w = _textbook_weight(e)
+    dim = 3 if q == 19 else 2
+    rng = np.random.default_rng(13)
+    for _ in range(10):
+        rho = rng.uniform(0.5, 1.5)
+        u = np.zeros(3)
+        u[:dim] = rng.normal(0, 0.1, dim)
+        f = O.bin_feq_site(bp, rho, rho * u, 0.0, np.zeros(3), 0.0)
+        eu = e @ u
+        want = w * rho * (1 + 3 * eu + 4.5 * eu ** 2 - 1.5 * u @ u)
+        np.testing.assert_allclose(f, want, atol=1e-15)
+
+
+@pytest.mark.parametrize("q,shape", [(9, (24, 20)), (19, (10, 9, 8))])
+def test_binary_conserves_mass_order_parameter_and_momentum(q, shape):
+    bp = O.bin_params(q=q, shape=shape, phi_a=PA, phi_b=PB, kappa=KAPPA, tau=0.8, tau_phi=1.3,
+                      gamma=0.8)
+    rng = np.random.default_rng(14)
+    n = int(np.prod(shape))
+    rho0 = 1 + 0.02 * rng.standard_normal(n)
+    phi0 = np.clip(rng.standard_normal(n), -1, 1) * 0.9
+    u0 = 0.02 * rng.standard_normal((3, n))
+    if q == 9:
+        u0[2] = 0
+    f, g = O.bin_init(bp, rho0, phi0, u0)
+    m0, p0, j0 = O.bin_totals(bp, f, g)
+    f, g = O.bin_run(bp, f, g, 300)
+    m1, p1, j1 = O.bin_totals(bp, f, g)
+    r, ph, v, mu = O.bin_observe(bp, f, g)
+    assert np.isfinite(v).all()
+    assert abs(m1 - m0) < 1e-12 * n
+    assert abs(p1 - p0) < 1e-12 * n
+    np.testing.assert_allclose(j1, j0, atol=1e-12 * n)
+    # the totals are the sums of the observed fields
+    assert abs(r.sum() - m1) < 1e-12 * n
+    assert abs(ph.sum() - p1) < 1e-12 * n
+    np.testing.assert_allclose((r * v).sum(1), j1, atol=1e-12 * n)
+
+
+def discrete_profile(phi_init, total, kappa=KAPPA):
+    """Periodic solution of psi'(phi) - kappa (phi_{x+1} - 2 phi_x + phi_{x-1})
+    = mu_0 with sum phi = total (Newton's method); returns (phi, mu_0)."""
+    n = phi_init.size
+    phi, mu0 = phi_init.astype(float).copy(), 0.0
+    idx = np.arange(n)
+    for _ in range(60):
+        lap = np.roll(phi, 1) + np.roll(phi, -1) - 2 * phi
+        res = np.concatenate([_dpsi(phi) - kappa * lap - mu0, [phi.sum() - total]])
+        J = np.zeros((n + 1, n + 1))
+        J[idx, idx] = PA + 3 * PB * phi ** 2 + 2 * kappa
+        J[idx, (idx + 1) % n] -= kappa
+        J[idx, (idx - 1) % n] -= kappa
+        J[:n, n] = -1
+        J[n, :n] = 1
+        d = np.linalg.solve(J, -res)
+        phi += d[:n]
+        mu0 += d[n]
+        if np.abs(d).max() < 1e-15:
+            break
+    return phi, mu0
+
+
+def _two_interfaces(nx, xi):
+    x = np.arange(nx) + 0.5
+    return np.tanh((x - nx / 4) / xi) * np.tanh((3 * nx / 4 - x) / xi)
+
+
+def test_discrete_profile_approaches_tanh_at_second_order():
+    errs = []
+    for kappa in (0.04, 0.16):  # xi = sqrt(-2 kappa / phi_a) = 2, 4
+        xi = np.sqrt(-2 * kappa / PA)
+        ref = _two_interfaces(128, xi)
+        phi, mu0 = discrete_profile(ref, ref.sum(), kappa)
+        assert abs(mu0) < 1e-10
+        errs.append(np.abs(phi - ref).max())
+    assert errs[1] < 5e-3
+    assert 3.0 < errs[0] / errs[1] < 5.0
+
+
+@pytest.mark.parametrize("q", [9, 19])
+def test_flat_interface_relaxes_to_the_discrete_steady_state(q):
+    nx = 64
+    shape = (nx, 2, 2) if q == 19 else (nx, 2)
+    bp = O.bin_params(q=q, shape=shape, phi_a=PA, phi_b=PB, kappa=KAPPA)
+    prof = _two_interfaces(nx, 2.0)
+    rows = int(np.prod(shape)) // nx
+    f, g = O.bin_init(bp, np.ones(rows * nx), np.tile(prof, rows))
+    total = O.bin_totals(bp, f, g)[1] / rows
+    ref, mu0 = discrete_profile(prof, total)
+    f, g = O.bin_run(bp, f, g, 40000)
+    r, ph, v, mu = O.bin_observe(bp, f, g)
+    ph = ph.reshape(rows, nx)
+    assert np.abs(ph - ref).max() < 1e-6
+    assert mu.max() - mu.min() < 1e-7
+    assert abs(mu.mean() - mu0) < 1e-10
+    assert np.abs(v).max() < 1e-10
+
+
+def _drop_umax(**over):
+    n, xi = 48, 2.0
+    bp = O.bin_params(q=9, shape=(n, n), phi_a=PA, phi_b=PB, kappa=KAPPA, **over)
+    yy, xx = np.mgrid[0:n, 0:n] + 0.5
+    phi0 = -np.tanh((np.hypot(xx - n / 2, yy - n / 2) - 12) / xi)
+    f, g = O.bin_init(bp, np.ones(n * n), phi0)
+    f, g = O.bin_run(bp, f, g, 4000)
+    v = O.bin_observe(bp, f, g)[2]
+    return np.sqrt((v ** 2).sum(0)).max()
+
+
+def test_optimum_stencils_suppress_binary_drop_spurious_velocities():
+    best = _drop_umax()
+    assert best < 2e-4
+    assert _drop_umax(B=0.0) > 3 * best
+    assert _drop_umax(wxx_d=0.0) > 3 * best
+
+
+def _cos_amp(bp, f, g, steps, field, k, rows, nx, comp=None):
+    f2, g2 = O.bin_run(bp, f, g, steps)
+    obs = O.bin_observe(bp, f2, g2)
+    v = obs[1] if field == "phi" else obs[2][comp]
+    v = v.reshape(rows, nx)[0]
+    x = np.arange(nx)
+    basis = np.cos(k * x) if field == "phi" else np.sin(k * x)
+    return 2 * np.mean(v * basis)
+
+
+@pytest.mark.parametrize("q", [9, 19])
+@pytest.mark.parametrize("tau_phi,gamma", [(1.3, 0.8), (0.8, 1.0)])
+def test_order_parameter_diffuses_with_mobility_gamma_tau_phi(q, tau_phi, gamma):
+    """One-phase region (phi_a > 0) about phi = 0: at linear order there is
+    no advection (phi u is second order) and no pressure perturbation, so a
+    mode cos(k x) decays at the rate gamma (tau_phi - 1/2) K (phi_a + kappa K),
+    K = 2 - 2 cos k the lattice Laplacian's eigenvalue (the Chapman-Enskog
+    mobility of a BGK scalar with second moment gamma mu)."""
+    nx, pa = 64, 0.02
+    shape = (nx, 2, 2) if q == 19 else (nx, 2)
+    rows = int(np.prod(shape)) // nx
+    bp = O.bin_params(q=q, shape=shape, phi_a=pa, phi_b=PB, kappa=KAPPA, tau=0.9,
+                      tau_phi=tau_phi, gamma=gamma)
+    k = 2 * np.pi / nx
+    f, g = O.bin_init(bp, np.ones(rows * nx), np.tile(1e-6 * np.cos(k * np.arange(nx)), rows))
+    a0 = _cos_amp(bp, f, g, 200, "phi", k, rows, nx)
+    a1 = _cos_amp(bp, f, g, 1200, "phi", k, rows, nx)
+    lk = 2 - 2 * np.cos(k)
+    want = gamma * (tau_phi - 0.5) * lk * (pa + KAPPA * lk)
+    assert abs(np.log(a0 / a1) / 1000 / want - 1) < 1e-2
+
+
+@pytest.mark.parametrize("q", [9, 19])
+def test_binary_shear_wave_decays_with_viscosity(q):
+    """Uniform phi = 1 with a shear wave u_y = U sin(k x): decay rate
+    nu k^2, nu = (tau - 1/2) / 3 (Eq. (viscous))."""
+    nx, tau = 64, 0.9
+    shape = (nx, 2, 2) if q == 19 else (nx, 2)
+    rows = int(np.prod(shape)) // nx
+    bp = O.bin_params(q=q, shape=shape, phi_a=PA, phi_b=PB, kappa=KAPPA, tau=tau, tau_phi=1.0)
+    k = 2 * np.pi / nx
+    u0 = np.zeros((3, rows * nx))
+    u0[1] = np.tile(1e-3 * np.sin(k * np.arange(nx)), rows)
+    f, g = O.bin_init(bp, np.ones(rows * nx), np.ones(rows * nx), u0)
+    a0 = _cos_amp(bp, f, g, 200, "u", k, rows, nx, comp=1)
+    a1 = _cos_amp(bp, f, g, 1200, "u", k, rows, nx, comp=1)
+    want = (tau - 0.5) / 3 * k ** 2
+    assert abs(np.log(a0 / a1) / 1000 / want - 1) < 2e-3
