@@ -369,6 +369,96 @@ int lbm_warm_project(int nprob, int side, int cpad, const float *dev_pred, const
                      double s_u, int with_velocity, int symmetrize, double rho_lo, double rho_hi, double *dev_rho,
                      double *dev_u, void *stream);
 
+/* ---- binary fluid -------------------------------------------------------
+ *
+ * The Introduction states that the analysis carries over to other multiphase
+ * systems such as binary fluids.  This stepper is that carry-over for the
+ * symmetric binary fluid: a carrier density rho with ideal-gas pressure
+ * rho/3 and an order parameter phi with bulk free energy
+ * phi_a phi^2/2 + phi_b phi^4/4 plus kappa |grad phi|^2/2 (phi_a < 0 gives
+ * two phases phi = +-sqrt(-phi_a/phi_b) with a tanh interface of width
+ * sqrt(-2 kappa/phi_a)).  Two FP64 distributions advance together on a
+ * periodic D2Q9 or D3Q19 lattice:
+ *   - f_i relaxes (time tau) to the tuned equilibrium of Eq. (equilibrium)/
+ *     (feq0) with phi in the place of the differentiated density: bulk
+ *     pressure rho/3 + phi_a phi^2/2 + 3 phi_b phi^4/4 on the w^p weights,
+ *     -w^t_i kappa phi lap(phi) and the w^ab_i kappa d_a phi d_b phi terms,
+ *     at the paper's optimum stencils and weights; no lambda term (it
+ *     vanishes for c_s^2 = 1/3, Eq. (viscous));
+ *   - g_i relaxes (time tau_phi) to the equilibrium with moments phi, phi u
+ *     and gamma mu delta_ab + phi u_a u_b, chemical potential
+ *     mu = phi_a phi + phi_b phi^3 - kappa lap(phi).
+ * Gradients and Laplacians use Eqs. (xderiv), (laplace), (laplacian3d).
+ * Fields and populations follow the conventions of the liquid-gas API
+ * (SoA, x fastest, post-streaming populations f_i(r,t) and g_i(r,t) in the
+ * paper's velocity numbering); the caller owns every buffer, and the
+ * context allocates no device memory. */
+typedef struct lbm_bin_ctx lbm_bin_ctx;
+
+typedef struct {
+    double phi_a, phi_b;  /* bulk free energy phi_a phi^2/2 + phi_b phi^4/4; phi_b >= 0 */
+    double kappa;         /* square-gradient coefficient, >= 0                     */
+    double gamma;         /* mobility coefficient of the mu term, >= 0             */
+    double tau, tau_phi;  /* relaxation times of f and g, Eq. (latbolt); > 1/2     */
+    int lattice;          /* LBM_D2Q9 or LBM_D3Q19                                 */
+    int nx, ny, nz;       /* lattice extent; nz = 1 for D2Q9                       */
+    int tile;             /* launch shape id (lbm_bin_tile_count); -1 = default    */
+    int planes_per_block; /* planes marched by one workgroup; <= 0 = default       */
+} lbm_bin_params;
+
+/* phi_a = -0.02, phi_b = 0.02, kappa = 0.04, gamma = 1, tau = tau_phi = 1,
+ * D2Q9 100 x 100, default launch. */
+void lbm_bin_params_default(lbm_bin_params *p);
+
+/* Bytes of device workspace (four population buffers, observation fields,
+ * reduction partials); 0 if the parameters are invalid. */
+size_t lbm_bin_workspace_bytes(const lbm_bin_params *p);
+
+/* Create a context with f = f^eq(rho0, rho0 u0, phi0) and g = g^eq(phi0,
+ * u0), the stencils applied to dev_phi0 [n]; dev_rho0 [n] must be finite and
+ * positive, dev_phi0 finite; dev_u0 [3][n] may be NULL (rest).
+ * dev_workspace (256-byte aligned) must stay valid until lbm_bin_destroy.
+ * LBM_E_INVAL for bad parameters or fields, LBM_E_NOMEM for a small
+ * workspace.  Synchronises the stream. */
+int lbm_bin_init(lbm_bin_ctx **out, const lbm_bin_params *p, void *dev_workspace, size_t bytes,
+                 void *stream, const double *dev_rho0, const double *dev_phi0, const double *dev_u0);
+
+/* Advance both distributions by nsteps >= 0 time steps (one fused launch
+ * per step).  Only enqueues work. */
+int lbm_bin_step(lbm_bin_ctx *ctx, long long nsteps);
+
+/* rho [n], phi [n], u = j / rho [3][n] and mu [n] of the current state; any
+ * pointer may be NULL.  Only enqueues work. */
+int lbm_bin_moments(lbm_bin_ctx *ctx, double *dev_rho, double *dev_phi, double *dev_vel,
+                    double *dev_mu);
+
+/* Maximum velocity magnitude max_r |u| (the spurious velocity of a static
+ * interface, Section "Numerical results"), FP64.  LBM_E_NONFINITE if the
+ * state holds a non-finite value or rho <= 0.  Synchronises. */
+int lbm_bin_max_spurious_u(lbm_bin_ctx *ctx, double *host_out);
+
+/* FP64 totals: mass sum f, order parameter sum g and momentum sum f e
+ * (host_mom[3]).  Synchronises. */
+int lbm_bin_invariants(lbm_bin_ctx *ctx, double *host_mass, double *host_phi, double *host_mom);
+
+/* Copy out / replace the state as post-streaming populations f_i(r,t),
+ * g_i(r,t), FP64 [q][n] each.  Only enqueue work. */
+int lbm_bin_get_state(lbm_bin_ctx *ctx, double *dev_f, double *dev_g);
+int lbm_bin_set_state(lbm_bin_ctx *ctx, const double *dev_f, const double *dev_g);
+
+/* Time steps taken since lbm_bin_init. */
+long long lbm_bin_steps_done(const lbm_bin_ctx *ctx);
+
+/* Launch shapes of the binary step (as lbm_tile_count / lbm_tile_shape /
+ * lbm_set_launch / lbm_get_launch); results do not depend on the shape. */
+int lbm_bin_tile_count(int lattice);
+int lbm_bin_tile_shape(int lattice, int k, int *tile_x, int *tile_y);
+int lbm_bin_set_launch(lbm_bin_ctx *ctx, int tile, int planes_per_block);
+int lbm_bin_get_launch(const lbm_bin_ctx *ctx, int *tile, int *planes_per_block, int *workgroups);
+
+/* Free the context (host memory only). */
+int lbm_bin_destroy(lbm_bin_ctx *ctx);
+
 /* ---- measurement --------------------------------------------------------
  *
  * Copy `bytes` (a multiple of 16, below 2^43; both pointers 16-byte aligned) from

@@ -234,6 +234,9 @@ def _bin_lib():
         L.orc_bin_feq_site.argtypes = [bp, ctypes.c_double, dp, ctypes.c_double, dp,
                                        ctypes.c_double, dp]
         L.orc_bin_geq_site.argtypes = [bp, ctypes.c_double, dp, ctypes.c_double, dp]
+        L.orc_bin_collide_sites.argtypes = [bp, dp, dp, ctypes.c_int,
+                                            ctypes.POINTER(ctypes.c_int), dp, dp]
+        L.orc_bin_collide_sites.restype = ctypes.c_int
         L._bin_ready = True
     return L
 
@@ -302,3 +305,16 @@ def bin_geq_site(bp, phi, u, lap):
     u = np.ascontiguousarray(u, dtype=np.float64)
     _bin_lib().orc_bin_geq_site(ctypes.byref(bp), float(phi), _p(u), float(lap), _p(out))
     return out
+
+
+def bin_collide_sites(bp, f, g, xyz):
+    """Post-collision (f*, g*) [nsite][q] at sites xyz[k] = (x, y, z)."""
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    g = np.ascontiguousarray(g, dtype=np.float64)
+    xyz = np.ascontiguousarray(xyz, dtype=np.int32).reshape(-1, 3)
+    fo = np.empty((xyz.shape[0], bp.base.q))
+    go = np.empty_like(fo)
+    _bin_lib().orc_bin_collide_sites(ctypes.byref(bp), _p(f), _p(g), xyz.shape[0],
+                                     xyz.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), _p(fo),
+                                     _p(go))
+    return fo, go

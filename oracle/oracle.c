@@ -955,3 +955,53 @@ void orc_bin_geq_site(const orc_bin_params *bp, double phi, const double *u, dou
     build_tables(&bp->base, &t);
     geq_bin_site_t(bp, &t, phi, u, bin_mu(bp, phi, lap), geq);
 }
+
+/* Post-collision populations f*_i(r), g*_i(r) (before streaming) of the
+ * binary fluid at a list of sites (x,y,z triples); fout, gout are
+ * [nsite][q].  After the step, f_i(r + e_i) = f*_i(r) and likewise g. */
+int orc_bin_collide_sites(const orc_bin_params *bp, const double *f, const double *g, int nsite,
+                          const int *xyz, double *fout, double *gout)
+{
+    if (!bin_valid(bp)) return -1;
+    const orc_params *p = &bp->base;
+    tables t;
+    build_tables(p, &t);
+    long n = nsites(p);
+    const double(*gs[3])[3][3] = {t.gx, t.gy, t.gz};
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int k = 0; k < nsite; k++) {
+        int x = xyz[3 * k], y = xyz[3 * k + 1], z = xyz[3 * k + 2];
+        long s = sidx(p, x, y, z);
+        double rho = 0, j[3] = {0, 0, 0};
+        for (int i = 0; i < t.q; i++) {
+            double v = f[i * n + s];
+            rho += v;
+            for (int a = 0; a < 3; a++) j[a] += v * t.e[i][a];
+        }
+        /* phi over the 3x3x3 neighbourhood, then the stencils */
+        double d[3] = {0, 0, 0}, lap = 0.0;
+        for (int sl = 0; sl < 3; sl++)
+            for (int r = 0; r < 3; r++)
+                for (int c = 0; c < 3; c++) {
+                    double kl = t.lap[sl][r][c];
+                    int any = kl != 0.0;
+                    for (int a = 0; a < t.dim; a++) any |= gs[a][sl][r][c] != 0.0;
+                    if (!any) continue;
+                    /* rho_at sums any distribution: here g, giving phi */
+                    double ph = rho_at(p, &t, g, x + c - 1, y + 1 - r, z + 1 - sl);
+                    for (int a = 0; a < t.dim; a++) d[a] += gs[a][sl][r][c] * ph;
+                    lap += kl * ph;
+                }
+        double phi = rho_at(p, &t, g, x, y, z);
+        double u[3] = {j[0] / rho, j[1] / rho, j[2] / rho};
+        double fe[19], ge[19];
+        feq_bin_site_t(bp, &t, rho, j, phi, d, lap, fe);
+        geq_bin_site_t(bp, &t, phi, u, bin_mu(bp, phi, lap), ge);
+        for (int i = 0; i < t.q; i++) {
+            double fi = f[i * n + s], gi = g[i * n + s];
+            fout[(long)k * t.q + i] = fi - (fi - fe[i]) / p->tau;
+            gout[(long)k * t.q + i] = gi - (gi - ge[i]) / bp->tau_phi;
+        }
+    }
+    return 0;
+}

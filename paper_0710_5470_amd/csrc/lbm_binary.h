@@ -1,0 +1,367 @@
+// lbm_binary.h -- fused time step of the binary-fluid free-energy model.
+//
+// The paper's Introduction states that its analysis applies equally to other
+// multiphase systems such as binary fluids.  This is that carry-over for the
+// symmetric binary fluid: an ideal-gas carrier density rho (c_s^2 = 1/3) and
+// an order parameter phi with bulk free energy pa phi^2/2 + pb phi^4/4 and
+// square-gradient term kappa |grad phi|^2 / 2.  Two distributions advance
+// together:
+//   f_i: the tuned equilibrium of Eq. (equilibrium)/(feq0) with phi in the
+//        place of the differentiated density: bulk pressure p0 = rho/3 +
+//        pa phi^2/2 + 3 pb phi^4/4 on the w^p weights, -w^t_i kappa phi
+//        lap(phi), and the w^ab_i kappa d_a phi d_b phi terms; the lambda
+//        term of Eq. (viscous) vanishes because c_s^2 = 1/3;
+//   g_i: an order-parameter distribution whose equilibrium has moments phi,
+//        phi u and gamma mu delta + phi u u, mu = pa phi + pb phi^3 -
+//        kappa lap(phi); the gamma mu term rides on the w^p weights, the
+//        velocity terms on w_i, and g_0 closes the zeroth moment.
+// Gradients and Laplacians of phi use the isotropic stencils of Eqs.
+// (xderiv), (laplace) and (laplacian3d); both distributions relax by BGK,
+// Eq. (latbolt), with times tau and tau_phi.
+//
+// Storage is FP64 in the pull layout of the liquid-gas kernels: S[i][r]
+// holds the post-collision population of direction i at its source site,
+// and the population arriving at r is S[i][r - e_i].
+//
+// March.  A workgroup owns an in-plane tile of TX x TY sites (TY = 1 for
+// D2Q9, whose "planes" are rows) and a chunk of consecutive planes.  Per
+// plane it (1) forms phi = sum_i g_i of the plane ahead, for the tile and a
+// one-site in-plane halo, into an LDS ring of four planes, then (2) after
+// one barrier collides the current plane: the stencils read the ring, the
+// own-site f_i and g_i are pulled again (the g values were fetched one plane
+// earlier, so they come from L2) and the collided values are stored at the
+// site itself, aligned.  With four ring slots the plane being formed is
+// never one still being read, so one barrier per plane suffices.
+#pragma once
+
+#include "lbm_aux.h"
+
+namespace lbm {
+
+struct BinCoefs {
+    double A, B;                 // gradient stencil: on-axis, off-axis
+    double C, D;                 // Laplacian stencil: on-axis, off-axis
+    double w_ax, w_off;          // velocity weights
+    double wp_ax, wp_off;        // w^p
+    double wt_ax, wt_off;        // w^t
+    double wm_para, wm_perp, wm_in, wm_out;  // w^aa classes (as Coefs)
+    double kappa;
+    double omega, omega_g;       // 1 / tau, 1 / tau_phi
+    double pa, pb;               // bulk free energy pa phi^2/2 + pb phi^4/4
+    double gamma;                // mobility coefficient of the mu term
+};
+
+struct BinArgs {
+    BinCoefs c;
+    const double *__restrict__ fsrc;
+    const double *__restrict__ gsrc;
+    double *__restrict__ fdst;
+    double *__restrict__ gdst;
+    int nx, ny, np;              // in-plane x, in-plane y (1 for D2Q9), planes
+    long long stride;            // elements between direction arrays
+    int tiles_x, tiles_y, cp;    // tiles per in-plane axis, planes per workgroup
+};
+
+template <class L> __device__ __forceinline__ double bin_grad_coef(const BinCoefs &c, int i)
+{
+    return nnz<L>(i) == 1 ? c.A : c.B;
+}
+template <class L> __device__ __forceinline__ double bin_lap_coef(const BinCoefs &c, int i)
+{
+    return nnz<L>(i) == 1 ? c.C : c.D;
+}
+
+// sum_ab w^ab_i kappa d_a phi d_b phi of velocity i; M[0..2] diagonal,
+// M[3..5] = xy, yz, zx
+template <class L> __device__ __forceinline__ double bin_m_terms(const BinCoefs &c, const double M[6], int i)
+{
+    const bool axis = nnz<L>(i) == 1;
+    double m = 0.0;
+#pragma unroll
+    for (int a = 0; a < L::DIM; a++) {
+        const bool touches = ecomp<L>(i, a) != 0;
+        m += (axis ? (touches ? c.wm_para : c.wm_perp) : (touches ? c.wm_in : c.wm_out)) * M[a];
+    }
+    const int e0 = L::ex[i], e1 = L::ey[i], e2 = L::ez[i];
+    if (e0 * e1 != 0) m += (0.25 * e0 * e1) * M[3];
+    if (e1 * e2 != 0) m += (0.25 * e1 * e2) * M[4];
+    if (e2 * e0 != 0) m += (0.25 * e2 * e0) * M[5];
+    return m;
+}
+
+// Collide both distributions at one site.  fin, gin: populations arriving at
+// the site; phi: sum of gin (formed by the caller in the same order as the
+// stencil's field); d, lap: gradient and Laplacian of phi.  emit_f(i, v) and
+// emit_g(i, v) receive the collided values.
+template <class L, class EF, class EG>
+__device__ __forceinline__ void bin_collide(const BinCoefs &c, const double fin[L::Q], const double gin[L::Q],
+                                            double phi, const double d[3], double lap, EF &&emit_f,
+                                            EG &&emit_g, double *obs = nullptr)
+{
+    constexpr int Q = L::Q, DIM = L::DIM;
+    double rho = 0.0, j[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int i = 0; i < Q; i++) {
+        rho += fin[i];
+        if (L::ex[i]) j[0] += L::ex[i] * fin[i];
+        if (L::ey[i]) j[1] += L::ey[i] * fin[i];
+        if (L::ez[i]) j[2] += L::ez[i] * fin[i];
+    }
+    const double inv = 1.0 / rho;
+    const double u[3] = {j[0] * inv, j[1] * inv, DIM == 3 ? j[2] * inv : 0.0};
+    const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    const double p2 = phi * phi;
+    const double p0 = rho * (1.0 / 3.0) + 0.5 * c.pa * p2 + 0.75 * c.pb * p2 * p2;
+    const double mu = c.pa * phi + c.pb * p2 * phi - c.kappa * lap;
+    double M[6] = {c.kappa * d[0] * d[0], c.kappa * d[1] * d[1], c.kappa * d[2] * d[2],
+                   c.kappa * d[0] * d[1], c.kappa * d[1] * d[2], c.kappa * d[2] * d[0]};
+    // per-class terms of f: w^p p0 - (3/2) w rho u^2 / 3 - w^t kappa phi lap
+    const double trX3 = rho * uu * (1.0 / 3.0);
+    const double klap = c.kappa * phi * lap;
+    const double stc[2] = {c.wp_ax * p0 - 1.5 * c.w_ax * trX3 - c.wt_ax * klap,
+                           c.wp_off * p0 - 1.5 * c.w_off * trX3 - c.wt_off * klap};
+    // per-class terms of g: w^p gamma mu - (3/2) w phi u^2 / 3
+    const double gmu = c.gamma * mu;
+    const double gtc[2] = {c.wp_ax * gmu - 0.5 * c.w_ax * phi * uu,
+                           c.wp_off * gmu - 0.5 * c.w_off * phi * uu};
+    const double om = c.omega, keep = 1.0 - om;
+    const double omg = c.omega_g, keepg = 1.0 - omg;
+    double sumE = 0.0, sumG = 0.0;
+#pragma unroll
+    for (int i = 1; i < Q; i++) {
+        if (opp<L>(i) < i) continue;
+        const int o = opp<L>(i);
+        const bool axis = nnz<L>(i) == 1;
+        const double w = axis ? c.w_ax : c.w_off;
+        const double eu = edot<L>(i, u);
+        // f: even = (3/2) w rho (e.u)^2 + class terms + w^ab terms; odd = w e.j
+        const double even = 1.5 * w * rho * eu * eu + stc[axis ? 0 : 1] + bin_m_terms<L>(c, M, i);
+        const double odd = w * edot<L>(i, j);
+        sumE += even;
+        emit_f(i, keep * fin[i] + om * (even + odd));
+        emit_f(o, keep * fin[o] + om * (even - odd));
+        // g: even = (3/2) w phi (e.u)^2 + class terms; odd = w phi e.u
+        const double geven = 1.5 * w * phi * eu * eu + gtc[axis ? 0 : 1];
+        const double godd = w * phi * eu;
+        sumG += geven;
+        emit_g(i, keepg * gin[i] + omg * (geven + godd));
+        emit_g(o, keepg * gin[o] + omg * (geven - godd));
+    }
+    emit_f(0, keep * fin[0] + om * (rho - 2.0 * sumE));
+    emit_g(0, keepg * gin[0] + omg * (phi - 2.0 * sumG));
+    if (obs) {
+        obs[0] = rho;
+        obs[1] = u[0];
+        obs[2] = u[1];
+        obs[3] = u[2];
+        obs[4] = mu;
+    }
+}
+
+// Wrapped coordinates of a column: value, value - 1, value + 1.
+__device__ __forceinline__ void wrap3(int v, int n, int (&w)[3])
+{
+    const int a = wrapg(v, n);
+    w[0] = a;
+    w[1] = a == 0 ? n - 1 : a - 1;
+    w[2] = a == n - 1 ? 0 : a + 1;
+}
+// the coordinate a population of offset o arrives from: x - o
+__device__ __forceinline__ int from3(const int (&w)[3], int o) { return o > 0 ? w[1] : (o < 0 ? w[2] : w[0]); }
+
+template <class L, int TX, int TY>
+__global__ __launch_bounds__(TX * TY) void bin_step_kernel(BinArgs a)
+{
+    constexpr int Q = L::Q, NT = TX * TY;
+    constexpr int HY = L::DIM == 3 ? 1 : 0;
+    constexpr int PW = TX + 2, PH = TY + 2 * HY, PL = PW * PH;
+    constexpr int NIT = (PL + NT - 1) / NT;
+    __shared__ double ring[4][PL];
+
+    const int tid = threadIdx.x;
+    int b = blockIdx.x;
+    const int bx = b % a.tiles_x;
+    b /= a.tiles_x;
+    const int by = b % a.tiles_y;
+    const int ch = b / a.tiles_y;
+    const int x0 = bx * TX, y0 = by * TY;
+    const int p_begin = ch * a.cp;
+    const int p_end = min(p_begin + a.cp, a.np);
+    const long long nxy = (long long)a.nx * a.ny;
+
+    // ring entries this thread forms: wrapped in-plane coordinates
+    int rx[NIT][3], ry[NIT][3];
+    bool rv[NIT];
+#pragma unroll
+    for (int k = 0; k < NIT; k++) {
+        const int e = tid + k * NT;
+        rv[k] = e < PL;
+        const int lx = e % PW - 1, ly = e / PW - HY;
+        wrap3(x0 + lx, a.nx, rx[k]);
+        wrap3(y0 + ly, a.ny, ry[k]);
+    }
+    // own site
+    const int tx = tid % TX, ty = tid / TX;
+    const int x = x0 + tx, y = y0 + ty;
+    const bool own = x < a.nx && y < a.ny;
+    int ox3[3], oy3[3];
+    wrap3(x, a.nx, ox3);
+    wrap3(y, a.ny, oy3);
+    const int c_own = (ty + HY) * PW + tx + 1;
+
+    auto src_index = [&](const int (&X)[3], const int (&Y)[3], const int (&P)[3], int i) {
+        return (long long)i * a.stride + (long long)from3(P, op<L>(i)) * nxy +
+               (long long)from3(Y, oy<L>(i)) * a.nx + from3(X, ox<L>(i));
+    };
+    // phi of plane p for every ring entry, into ring slot s
+    auto form_phi = [&](int p, int s) {
+        int P[3];
+        wrap3(p, a.np, P);
+#pragma unroll
+        for (int k = 0; k < NIT; k++) {
+            if (!rv[k]) continue;
+            double v = 0.0;
+#pragma unroll
+            for (int i = 0; i < Q; i++) v += a.gsrc[src_index(rx[k], ry[k], P, i)];
+            ring[s][tid + k * NT] = v;
+        }
+    };
+
+    form_phi(p_begin - 1, 0);
+    form_phi(p_begin, 1);
+    for (int t = 0; p_begin + t < p_end; t++) {
+        form_phi(p_begin + t + 1, (t + 2) & 3);
+        __syncthreads();
+        if (!own) continue;
+        const int p = p_begin + t;
+        const double *sl[3] = {ring[t & 3], ring[(t + 1) & 3], ring[(t + 2) & 3]};
+        const double phi = sl[1][c_own];
+        double d[3] = {0.0, 0.0, 0.0}, lap = 0.0;
+#pragma unroll
+        for (int i = 1; i < Q; i++) {
+            const double v = sl[1 + op<L>(i)][c_own + oy<L>(i) * PW + ox<L>(i)];
+            const double g = bin_grad_coef<L>(a.c, i) * v;
+            if (L::ex[i]) d[0] += L::ex[i] * g;
+            if (L::ey[i]) d[1] += L::ey[i] * g;
+            if (L::ez[i]) d[2] += L::ez[i] * g;
+            lap += bin_lap_coef<L>(a.c, i) * (v - phi);
+        }
+        int P[3];
+        wrap3(p, a.np, P);
+        double fin[Q], gin[Q];
+#pragma unroll
+        for (int i = 0; i < Q; i++) {
+            const long long s = src_index(ox3, oy3, P, i);
+            fin[i] = a.fsrc[s];
+            gin[i] = a.gsrc[s];
+        }
+        const long long site = (long long)p * nxy + (long long)y * a.nx + x;
+        bin_collide<L>(
+            a.c, fin, gin, phi, d, lap,
+            [&](int i, double v) { __builtin_nontemporal_store(v, a.fdst + (long long)i * a.stride + site); },
+            [&](int i, double v) { __builtin_nontemporal_store(v, a.gdst + (long long)i * a.stride + site); });
+    }
+}
+
+// f = f^eq(rho0, rho0 u0, phi0), g = g^eq(phi0, u0) with the stencils applied
+// to phi0, stored in the pull layout (at r - e_i).
+template <class L>
+__global__ void bin_init_kernel(Geom g, BinCoefs c, const double *__restrict__ rho0,
+                                const double *__restrict__ phi0, const double *__restrict__ u0,
+                                double *__restrict__ fdst, double *__restrict__ gdst)
+{
+    const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= g.n) return;
+    int x, y, p;
+    site_coords<L>(g, s, x, y, p);
+    const double phi = phi0[s], rho = rho0[s];
+    double d[3] = {0, 0, 0}, lap = 0;
+#pragma unroll
+    for (int i = 1; i < L::Q; i++) {
+        const double v = phi0[neighbour<L>(g, x, y, p, i, +1)];
+        const double cg = bin_grad_coef<L>(c, i) * v;
+        d[0] += L::ex[i] * cg;
+        d[1] += L::ey[i] * cg;
+        d[2] += L::ez[i] * cg;
+        lap += bin_lap_coef<L>(c, i) * (v - phi);
+    }
+    double u[3] = {0, 0, 0};
+    if (u0) {
+        u[0] = u0[s];
+        u[1] = u0[g.stride + s];
+        if (L::DIM == 3) u[2] = u0[2 * g.stride + s];
+    }
+    // equilibria = collision with omega = 1 of any populations with these
+    // moments: feed the equilibrium moments through a rest-only input
+    BinCoefs ce = c;
+    ce.omega = 1.0;
+    ce.omega_g = 1.0;
+    double fin[L::Q], gin[L::Q];
+#pragma unroll
+    for (int i = 0; i < L::Q; i++) {
+        fin[i] = 0.0;
+        gin[i] = 0.0;
+    }
+    // populations carrying mass rho and momentum rho u: rest + one pair per axis
+    fin[0] = rho;
+    gin[0] = phi;
+#pragma unroll
+    for (int a = 0; a < L::DIM; a++) {
+        // velocity +e_a is index 1 + 2a (paper numbering: axes first, +/- pairs)
+        const double half = 0.5 * rho * u[a];
+        fin[1 + 2 * a] += half;
+        fin[2 + 2 * a] -= half;
+    }
+    bin_collide<L>(
+        ce, fin, gin, phi, d, lap,
+        [&](int i, double v) { fdst[(long long)i * g.stride + neighbour<L>(g, x, y, p, i, -1)] = v; },
+        [&](int i, double v) { gdst[(long long)i * g.stride + neighbour<L>(g, x, y, p, i, -1)] = v; });
+}
+
+// Observables of the pulled state: rho, phi, u = j / rho (for mu, a second
+// pass applies the Laplacian to phi).
+template <class L>
+__global__ void bin_moments_kernel(Geom g, const double *__restrict__ fsrc, const double *__restrict__ gsrc,
+                                   double *__restrict__ rho_out, double *__restrict__ phi_out,
+                                   double *__restrict__ vel_out)
+{
+    const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= g.n) return;
+    int x, y, p;
+    site_coords<L>(g, s, x, y, p);
+    double rho = 0, phi = 0, j[3] = {0, 0, 0};
+#pragma unroll
+    for (int i = 0; i < L::Q; i++) {
+        const long long k = (long long)i * g.stride + neighbour<L>(g, x, y, p, i, -1);
+        const double v = fsrc[k];
+        rho += v;
+        phi += gsrc[k];
+        j[0] += L::ex[i] * v;
+        j[1] += L::ey[i] * v;
+        j[2] += L::ez[i] * v;
+    }
+    if (rho_out) rho_out[s] = rho;
+    if (phi_out) phi_out[s] = phi;
+    if (vel_out) {
+        vel_out[s] = j[0] / rho;
+        vel_out[g.stride + s] = j[1] / rho;
+        vel_out[2 * g.stride + s] = L::DIM == 3 ? j[2] / rho : 0.0;
+    }
+}
+
+// mu = pa phi + pb phi^3 - kappa lap(phi) from a phi field
+template <class L>
+__global__ void bin_mu_kernel(Geom g, BinCoefs c, const double *__restrict__ phi, double *__restrict__ mu)
+{
+    const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= g.n) return;
+    int x, y, p;
+    site_coords<L>(g, s, x, y, p);
+    const double v0 = phi[s];
+    double lap = 0;
+#pragma unroll
+    for (int i = 1; i < L::Q; i++) lap += bin_lap_coef<L>(c, i) * (phi[neighbour<L>(g, x, y, p, i, +1)] - v0);
+    mu[s] = c.pa * v0 + c.pb * v0 * v0 * v0 - c.kappa * lap;
+}
+
+} // namespace lbm

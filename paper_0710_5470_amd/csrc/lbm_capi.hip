@@ -770,3 +770,4 @@ int lbm_coexistence(double a, double b, double T, double *rho_gas, double *rho_l
 
 #include "lbm_batch_host.h"
 #include "lbm_net_host.h"
+#include "lbm_binary_host.h"

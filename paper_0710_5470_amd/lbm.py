@@ -118,6 +118,34 @@ _sig.update({
                                         ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int,
                                         ctypes.c_double, ctypes.c_double, _vp, _vp, _vp]),
 })
+class lbm_bin_params(ctypes.Structure):
+    _fields_ = [
+        ("phi_a", ctypes.c_double), ("phi_b", ctypes.c_double), ("kappa", ctypes.c_double),
+        ("gamma", ctypes.c_double), ("tau", ctypes.c_double), ("tau_phi", ctypes.c_double),
+        ("lattice", ctypes.c_int), ("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
+        ("tile", ctypes.c_int), ("planes_per_block", ctypes.c_int),
+    ]
+
+
+_bp = ctypes.POINTER(lbm_bin_params)
+_sig.update({
+    "lbm_bin_params_default": (None, [_bp]),
+    "lbm_bin_workspace_bytes": (ctypes.c_size_t, [_bp]),
+    "lbm_bin_init": (ctypes.c_int, [ctypes.POINTER(_vp), _bp, _vp, ctypes.c_size_t, _vp, _vp, _vp,
+                                    _vp]),
+    "lbm_bin_step": (ctypes.c_int, [_vp, ctypes.c_longlong]),
+    "lbm_bin_moments": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
+    "lbm_bin_max_spurious_u": (ctypes.c_int, [_vp, _dp]),
+    "lbm_bin_invariants": (ctypes.c_int, [_vp, _dp, _dp, _dp]),
+    "lbm_bin_get_state": (ctypes.c_int, [_vp, _vp, _vp]),
+    "lbm_bin_set_state": (ctypes.c_int, [_vp, _vp, _vp]),
+    "lbm_bin_steps_done": (ctypes.c_longlong, [_vp]),
+    "lbm_bin_tile_count": (ctypes.c_int, [ctypes.c_int]),
+    "lbm_bin_tile_shape": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _ip, _ip]),
+    "lbm_bin_set_launch": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int]),
+    "lbm_bin_get_launch": (ctypes.c_int, [_vp, _ip, _ip, _ip]),
+    "lbm_bin_destroy": (ctypes.c_int, [_vp]),
+})
 BATCH_RUNNING, BATCH_CONVERGED, BATCH_MAXSTEPS, BATCH_DIVERGED, BATCH_NONFINITE = 0, 1, 2, 3, 4
 for _name, (_res, _args) in _sig.items():
     _f = getattr(_L, _name)
@@ -557,3 +585,165 @@ def params(lattice=D2Q9, scheme=SCHEME_EQ, storage=STORE_F64, shape=(64, 64), a=
 
 
 NAN = math.nan
+
+
+# ---- binary fluid -------------------------------------------------------------
+
+def lbm_bin_params_default(**over):
+    p = lbm_bin_params()
+    _L.lbm_bin_params_default(ctypes.byref(p))
+    for k, v in over.items():
+        setattr(p, k, v)
+    return p
+
+
+def lbm_bin_workspace_bytes(p):
+    return int(_L.lbm_bin_workspace_bytes(ctypes.byref(p)))
+
+
+def lbm_bin_init(p, workspace, rho0, phi0, u0=None, stream=None):
+    ctx = ctypes.c_void_p()
+    rc = _L.lbm_bin_init(ctypes.byref(ctx), ctypes.byref(p), _ptr(workspace),
+                         workspace.numel() * workspace.element_size(), _stream(stream), _ptr(rho0),
+                         _ptr(phi0), _ptr(u0))
+    _check(rc, "lbm_bin_init")
+    return ctx
+
+
+def lbm_bin_step(ctx, nsteps):
+    _check(_L.lbm_bin_step(ctx, int(nsteps)), "lbm_bin_step")
+
+
+def lbm_bin_moments(ctx, rho=None, phi=None, vel=None, mu=None):
+    _check(_L.lbm_bin_moments(ctx, _ptr(rho), _ptr(phi), _ptr(vel), _ptr(mu)), "lbm_bin_moments")
+
+
+def lbm_bin_max_spurious_u(ctx):
+    out = ctypes.c_double()
+    _check(_L.lbm_bin_max_spurious_u(ctx, ctypes.byref(out)), "lbm_bin_max_spurious_u")
+    return out.value
+
+
+def lbm_bin_invariants(ctx):
+    m, ph = ctypes.c_double(), ctypes.c_double()
+    mom = (ctypes.c_double * 3)()
+    _check(_L.lbm_bin_invariants(ctx, ctypes.byref(m), ctypes.byref(ph), mom), "lbm_bin_invariants")
+    return m.value, ph.value, list(mom)
+
+
+def lbm_bin_get_state(ctx, f, g):
+    _check(_L.lbm_bin_get_state(ctx, _ptr(f), _ptr(g)), "lbm_bin_get_state")
+
+
+def lbm_bin_set_state(ctx, f, g):
+    _check(_L.lbm_bin_set_state(ctx, _ptr(f), _ptr(g)), "lbm_bin_set_state")
+
+
+def lbm_bin_steps_done(ctx):
+    return int(_L.lbm_bin_steps_done(ctx))
+
+
+def lbm_bin_tile_count(lattice):
+    return int(_L.lbm_bin_tile_count(int(lattice)))
+
+
+def lbm_bin_tile_shape(lattice, k):
+    tx, ty = ctypes.c_int(), ctypes.c_int()
+    _check(_L.lbm_bin_tile_shape(int(lattice), int(k), ctypes.byref(tx), ctypes.byref(ty)),
+           "lbm_bin_tile_shape")
+    return tx.value, ty.value
+
+
+def lbm_bin_set_launch(ctx, tile=-1, planes=0):
+    _check(_L.lbm_bin_set_launch(ctx, int(tile), int(planes)), "lbm_bin_set_launch")
+
+
+def lbm_bin_get_launch(ctx):
+    t, c, w = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    _check(_L.lbm_bin_get_launch(ctx, ctypes.byref(t), ctypes.byref(c), ctypes.byref(w)),
+           "lbm_bin_get_launch")
+    return t.value, c.value, w.value
+
+
+def lbm_bin_destroy(ctx):
+    _check(_L.lbm_bin_destroy(ctx), "lbm_bin_destroy")
+
+
+def bin_params(lattice=D2Q9, shape=(64, 64), phi_a=-0.02, phi_b=0.02, kappa=0.04, gamma=1.0,
+               tau=1.0, tau_phi=1.0, **over):
+    """lbm_bin_params from keyword arguments; shape = (nx, ny[, nz])."""
+    nz = shape[2] if len(shape) > 2 else 1
+    return lbm_bin_params_default(phi_a=phi_a, phi_b=phi_b, kappa=kappa, gamma=gamma, tau=tau,
+                                  tau_phi=tau_phi, lattice=lattice, nx=shape[0], ny=shape[1],
+                                  nz=nz, **over)
+
+
+class BinarySimulation:
+    """Owns one binary-fluid context and its workspace (fields as numpy
+    arrays or torch tensors, x fastest)."""
+
+    def __init__(self, params, rho0, phi0, u0=None, device="cuda", stream=None):
+        self.p = params
+        self.q = params.lattice
+        self.n = params.nx * params.ny * params.nz
+        self.device = torch.device(device)
+        nbytes = lbm_bin_workspace_bytes(params)
+        if nbytes == 0:
+            raise LBMError(E_INVAL, "lbm_bin_workspace_bytes")
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+
+        def dev(a, ncomp=None):
+            t = torch.as_tensor(a, dtype=torch.float64)
+            t = t.reshape(-1) if ncomp is None else t.reshape(ncomp, -1)
+            return t.to(self.device).contiguous()
+
+        self.ctx = lbm_bin_init(params, self.ws, dev(rho0), dev(phi0),
+                                None if u0 is None else dev(u0, 3), stream)
+
+    def step(self, n):
+        lbm_bin_step(self.ctx, n)
+
+    def moments(self):
+        """(rho[n], phi[n], u[3][n], mu[n])."""
+        t = [torch.empty(s, dtype=torch.float64, device=self.device)
+             for s in (self.n, self.n, (3, self.n), self.n)]
+        lbm_bin_moments(self.ctx, *t)
+        return tuple(t)
+
+    def max_spurious_u(self):
+        return lbm_bin_max_spurious_u(self.ctx)
+
+    def invariants(self):
+        return lbm_bin_invariants(self.ctx)
+
+    def get_state(self):
+        f = torch.empty(self.q, self.n, dtype=torch.float64, device=self.device)
+        g = torch.empty_like(f)
+        lbm_bin_get_state(self.ctx, f, g)
+        return f, g
+
+    def set_state(self, f, g):
+        f = torch.as_tensor(f, dtype=torch.float64).reshape(self.q, self.n).to(self.device)
+        g = torch.as_tensor(g, dtype=torch.float64).reshape(self.q, self.n).to(self.device)
+        lbm_bin_set_state(self.ctx, f.contiguous(), g.contiguous())
+
+    def set_launch(self, tile=-1, planes=0):
+        lbm_bin_set_launch(self.ctx, tile, planes)
+
+    def launch(self):
+        return lbm_bin_get_launch(self.ctx)
+
+    @property
+    def steps_done(self):
+        return lbm_bin_steps_done(self.ctx)
+
+    def close(self):
+        if self.ctx is not None:
+            lbm_bin_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,218 @@
+"""GPU parity of the binary-fluid stepper: the HIP library (through its C
+ABI) against the FP64 CPU oracle.
+
+Populations f and g, the observables rho, phi, u, mu and the FP64
+reductions (totals, max |u|) within 1e-12 of the oracle (relative for
+populations, densities and totals, absolute for velocities and mu); launch
+shapes bitwise equal to one another.  Sizes span several tiles, ragged
+tails, fewer planes than the ring holds and wrap-around in every direction.
+Inputs: a drop of phi = +1 in phi = -1 (tanh profile of width 2), density
+and velocity noise from the shared seeded generators.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+PA, PB, KAPPA = -0.02, 0.02, 0.04
+
+
+def _lbm():
+    from paper_0710_5470_amd import lbm
+    return lbm
+
+
+def _say(*a):
+    print("[gpu-case]", *a, flush=True)
+
+
+def _fields(shape, noise=True, seed=21):
+    from paper_0710_5470_amd import inputs
+    n = int(np.prod(shape))
+    R = min(shape[:2]) / 4.0
+    phi = inputs.tanh_drop(shape, R, 1.0, -1.0, 2.0).reshape(-1)
+    rho = np.ones(n)
+    u = np.zeros((3, n))
+    if noise:
+        rho = rho + inputs.uniform_noise(shape, 0.02, seed).reshape(-1)
+        for a in range(len(shape)):
+            u[a] = inputs.uniform_noise(shape, 0.02, seed + 1 + a).reshape(-1)
+    return rho, phi, u
+
+
+def _pair(q, shape, **kw):
+    import oracle
+    lbm = _lbm()
+    kw = dict(dict(phi_a=PA, phi_b=PB, kappa=KAPPA), **kw)
+    return lbm.bin_params(lattice=q, shape=shape, **kw), oracle.bin_params(q=q, shape=shape, **kw)
+
+
+def _gpu_run(gp, rho, phi, u, nsteps, tile=-1, planes=0):
+    lbm = _lbm()
+    _say("binary q", gp.lattice, "shape", (gp.nx, gp.ny, gp.nz), "steps", nsteps, "tile", tile,
+         "planes", planes)
+    sim = lbm.BinarySimulation(gp, rho, phi, u)
+    if tile >= 0 or planes > 0:
+        sim.set_launch(tile, planes)
+    sim.step(nsteps)
+    f, g = [t.cpu().numpy() for t in sim.get_state()]
+    obs = [t.cpu().numpy() for t in sim.moments()]
+    return sim, f, g, obs
+
+
+CASES = [
+    (9, (64, 48), 120, {}), (9, (37, 29), 80, dict(tau=0.8, tau_phi=1.3, gamma=0.7)),
+    (9, (300, 5), 40, {}), (9, (33, 2), 30, {}), (9, (5, 3), 20, {}),
+    (19, (24, 20, 18), 60, {}), (19, (37, 11, 9), 40, dict(tau=0.7, tau_phi=1.1, gamma=1.2)),
+    (19, (70, 19, 5), 30, {}), (19, (13, 9, 2), 30, {}), (19, (16, 12, 1), 20, {}),
+    (19, (3, 4, 2), 20, {}),
+]
+
+
+@pytest.mark.parametrize("q,shape,nsteps,kw", CASES)
+def test_binary_matches_oracle(q, shape, nsteps, kw):
+    import oracle
+    gp, op = _pair(q, shape, **kw)
+    rho, phi, u = _fields(shape)
+    sim, f_g, g_g, (r_g, p_g, v_g, m_g) = _gpu_run(gp, rho, phi, u, nsteps)
+    f_o, g_o = oracle.bin_init(op, rho, phi, u)
+    f_o, g_o = oracle.bin_run(op, f_o, g_o, nsteps)
+    r_o, p_o, v_o, m_o = oracle.bin_observe(op, f_o, g_o)
+    ef, eg = np.abs(f_g - f_o).max(), np.abs(g_g - g_o).max()
+    ev, em = np.abs(v_g - v_o).max(), np.abs(m_g - m_o).max()
+    _say("err f", ef, "g", eg, "u", ev, "mu", em)
+    assert ef < 1e-12 * np.abs(f_o).max()
+    assert eg < 1e-12 * np.abs(g_o).max()
+    np.testing.assert_allclose(r_g, r_o, rtol=1e-12, atol=0)
+    assert np.abs(p_g - p_o).max() < 1e-12
+    assert ev < 1e-12
+    assert em < 1e-12
+    # FP64 reductions against the oracle's totals and observables
+    m, ph, mom = sim.invariants()
+    mo, pho, momo = oracle.bin_totals(op, f_o, g_o)
+    n = f_o.shape[1]
+    assert abs(m - mo) < 1e-12 * abs(mo)
+    assert abs(ph - pho) < 1e-12 * n
+    np.testing.assert_allclose(mom, momo, rtol=0, atol=1e-12 * n)
+    umax = sim.max_spurious_u()
+    assert abs(umax - np.sqrt((v_o ** 2).sum(0)).max()) < 1e-12
+    sim.close()
+
+
+@pytest.mark.parametrize("q,shape", [(9, (200, 37)), (19, (70, 21, 13))])
+def test_binary_launch_shapes_agree_bitwise(q, shape):
+    lbm = _lbm()
+    gp, _ = _pair(q, shape, tau=0.9, tau_phi=1.2)
+    rho, phi, u = _fields(shape)
+    ref = None
+    for tile in range(lbm.lbm_bin_tile_count(q)):
+        for planes in (1, 3, 16, 1000):
+            sim, f, g, _ = _gpu_run(gp, rho, phi, u, 12, tile, planes)
+            sim.close()
+            if ref is None:
+                ref = (f, g)
+                continue
+            assert np.array_equal(f, ref[0]) and np.array_equal(g, ref[1]), (tile, planes)
+
+
+@pytest.mark.parametrize("q,shape", [(9, (40, 31)), (19, (20, 13, 9))])
+def test_binary_state_round_trip_and_steps_from_oracle_state(q, shape):
+    """set_state of an oracle state returns it bitwise, and stepping from it
+    matches the oracle stepping from the same state."""
+    import oracle
+    gp, op = _pair(q, shape)
+    rho, phi, u = _fields(shape, seed=31)
+    f_o, g_o = oracle.bin_run(op, *oracle.bin_init(op, rho, phi, u), 25)
+    lbm = _lbm()
+    sim = lbm.BinarySimulation(gp, np.ones(f_o.shape[1]), np.zeros(f_o.shape[1]))
+    sim.set_state(f_o, g_o)
+    f, g = [t.cpu().numpy() for t in sim.get_state()]
+    assert np.array_equal(f, f_o) and np.array_equal(g, g_o)
+    sim.step(10)
+    f, g = [t.cpu().numpy() for t in sim.get_state()]
+    f_o, g_o = oracle.bin_run(op, f_o, g_o, 10)
+    assert np.abs(f - f_o).max() < 1e-12 and np.abs(g - g_o).max() < 1e-12
+    assert sim.steps_done == 10
+    sim.close()
+
+
+def test_binary_rejects_bad_input():
+    lbm = _lbm()
+    gp, _ = _pair(9, (16, 16))
+    for bad in (dict(tau=0.5), dict(tau_phi=0.4), dict(phi_b=-1.0), dict(kappa=-0.1),
+                dict(gamma=float("nan")), dict(tile=5), dict(nz=2)):
+        p = lbm.bin_params(lattice=9, shape=(16, 16), **bad) if "nz" not in bad else \
+            lbm.bin_params(lattice=9, shape=(16, 16, 2))
+        assert lbm.lbm_bin_workspace_bytes(p) == 0, bad
+    rho, phi, u = _fields((16, 16), noise=False)
+    rho[3] = 0.0
+    with pytest.raises(lbm.LBMError):
+        lbm.BinarySimulation(gp, rho, phi)
+    rho[3] = 1.0
+    phi[5] = np.nan
+    with pytest.raises(lbm.LBMError):
+        lbm.BinarySimulation(gp, rho, phi)
+
+
+def test_binary_flat_interface_relaxes_to_the_oracle_steady_state():
+    """Long run: 20000 steps of a flat interface pair agree with the oracle
+    and keep the invariants (both at steady state, mu uniform)."""
+    import oracle
+    from paper_0710_5470_amd import inputs
+    shape = (64, 4)
+    gp, op = _pair(9, shape)
+    phi = inputs.flat_slab(64, 4, 1.0, -1.0, 16.0, 2.0).reshape(-1)
+    rho = np.ones_like(phi)
+    sim, f, g, (r, p, v, mu) = _gpu_run(gp, rho, phi, None, 20000)
+    f_o, g_o = oracle.bin_run(op, *oracle.bin_init(op, rho, phi), 20000)
+    assert np.abs(f - f_o).max() < 1e-11 and np.abs(g - g_o).max() < 1e-11
+    assert mu.max() - mu.min() < 1e-6
+    assert np.abs(v).max() < 1e-8
+    sim.close()
+
+
+FULL = [("d3q19_256_fp64_binary", 19, (256, 256, 256)), ("d2q9_1024_fp64_binary", 9, (1024, 1024))]
+
+
+@pytest.mark.parametrize("name,q,shape", FULL)
+def test_full_size_binary_matches_oracle_on_sampled_sites(name, q, shape):
+    """The benchmark's lattices in its default launch: after one step the
+    populations arriving from 512 sampled sites equal the oracle's
+    site-local collision there; the state stays finite and conserves its
+    totals over 50 further steps."""
+    import oracle
+    from paper_0710_5470_amd import inputs
+    lbm = _lbm()
+    gp, op = _pair(q, shape)
+    n = int(np.prod(shape))
+    R = shape[0] / 4.0
+    phi = inputs.tanh_drop(shape, R, 1.0, -1.0, 2.0).reshape(-1)
+    rho = 1.0 + inputs.uniform_noise(shape, 0.01, 41).reshape(-1)
+    _say("full-size binary", name)
+    sim = lbm.BinarySimulation(gp, rho, phi)
+    f0, g0 = [t.cpu().numpy() for t in sim.get_state()]
+    sim.step(1)
+    f1, g1 = [t.cpu().numpy() for t in sim.get_state()]
+    rng = np.random.default_rng(5)
+    nz = shape[2] if q == 19 else 1
+    xyz = np.stack([rng.integers(0, shape[0], 512), rng.integers(0, shape[1], 512),
+                    rng.integers(0, nz, 512)], 1)
+    # include the lattice's corners (wrap-around in every direction)
+    xyz[:2] = [[0, 0, 0], [shape[0] - 1, shape[1] - 1, nz - 1]]
+    fo, go = oracle.bin_collide_sites(op, f0, g0, xyz)
+    e = oracle.tables(op.base)["e"]
+    for i in range(q):
+        dst = (((xyz[:, 2] + e[i, 2]) % nz) * shape[1] + (xyz[:, 1] + e[i, 1]) % shape[1]) \
+            * shape[0] + (xyz[:, 0] + e[i, 0]) % shape[0]
+        assert np.abs(f1[i, dst] - fo[:, i]).max() < 1e-13
+        assert np.abs(g1[i, dst] - go[:, i]).max() < 1e-13
+    del f0, g0, f1, g1
+    m0, p0, j0 = sim.invariants()
+    sim.step(50)
+    m1, p1, j1 = sim.invariants()
+    assert abs(m1 - m0) < 1e-12 * abs(m0)
+    assert abs(p1 - p0) < 1e-12 * n
+    assert np.abs(np.array(j1) - np.array(j0)).max() < 1e-12 * n
+    assert np.isfinite(sim.max_spurious_u())
+    sim.close()

@@ -262,3 +262,30 @@ def test_binary_shear_wave_decays_with_viscosity(q):
     a1 = _cos_amp(bp, f, g, 1200, "u", k, rows, nx, comp=1)
     want = (tau - 0.5) / 3 * k ** 2
     assert abs(np.log(a0 / a1) / 1000 / want - 1) < 2e-3
+
+
+@pytest.mark.parametrize("q,shape", [(9, (13, 11)), (19, (7, 6, 5))])
+def test_site_local_collision_matches_the_stepper(q, shape):
+    """The site-local evaluation (used to check large lattices at sampled
+    sites) gives the stepper's post-collision values: after one step the
+    population arriving at r + e_i is the one collided at r."""
+    bp = O.bin_params(q=q, shape=shape, phi_a=PA, phi_b=PB, kappa=KAPPA, tau=0.8, tau_phi=1.2,
+                      gamma=0.9)
+    rng = np.random.default_rng(15)
+    n = int(np.prod(shape))
+    u0 = 0.03 * rng.standard_normal((3, n))
+    if q == 9:
+        u0[2] = 0
+    f, g = O.bin_init(bp, 1 + 0.05 * rng.standard_normal(n), 0.9 * np.tanh(rng.standard_normal(n)),
+                      u0)
+    f1, g1 = O.bin_run(bp, f, g, 1)
+    e = O.tables(bp.base)["e"]
+    nx, ny = shape[0], shape[1]
+    nz = shape[2] if q == 19 else 1
+    xyz = np.array([(x, y, z) for z in range(nz) for y in range(ny) for x in range(nx)])
+    fo, go = O.bin_collide_sites(bp, f, g, xyz)
+    for i in range(q):
+        dst = (((xyz[:, 2] + e[i, 2]) % nz) * ny + (xyz[:, 1] + e[i, 1]) % ny) * nx \
+            + (xyz[:, 0] + e[i, 0]) % nx
+        np.testing.assert_allclose(f1[i, dst], fo[:, i], rtol=0, atol=1e-15)
+        np.testing.assert_allclose(g1[i, dst], go[:, i], rtol=0, atol=1e-15)
