@@ -41,6 +41,16 @@ WORKLOADS = {
     "d2q9_1024_fp32_eq": (9, 0, 1, 0, (1024, 1024), 0.56, 0.01, 1.0, 28.0, 0.0),
     "d2q9_1024_fp32_force": (9, 1, 1, 0, (1024, 1024), 0.56, 0.01, 1.0, 28.0, 0.0),
 }
+# binary fluid (FP64 f and g): name: (lattice, shape); phi_a = -0.02,
+# phi_b = 0.02, kappa = 0.04, gamma = 1, tau = tau_phi = 1; a drop of
+# phi = +1 (radius side/4, tanh width 2) in phi = -1, rho = 1 + noise 0.01
+BIN_WORKLOADS = {
+    "d3q19_256_fp64_binary": (19, (256, 256, 256)),
+    "d2q9_1024_fp64_binary": (9, (1024, 1024)),
+}
+BIN_PARAMS = dict(phi_a=-0.02, phi_b=0.02, kappa=0.04, gamma=1.0, tau=1.0, tau_phi=1.0)
+BIN_KERNEL_SOURCES = ["paper_0710_5470_amd/csrc/lbm_binary.h", "paper_0710_5470_amd/csrc/lbm_lattice.h",
+                      "paper_0710_5470_amd/build.py"]
 # residual target of the FP32 uneven batch: 2.5x above the highest FP32
 # floor seen among its 512 problems (about 2e-8)
 UNEVEN_TOL_F32 = 5e-8
@@ -71,10 +81,10 @@ def _code_only(text):
     return "\n".join(line.rstrip() for line in text.splitlines() if line.strip())
 
 
-def kernel_hash(sources=None):
+def kernel_hash(sources=None, files=None):
     """Hash of the step kernel's code (comments and blank lines excluded)."""
     h = hashlib.sha256()
-    for rel in KERNEL_SOURCES:
+    for rel in files or KERNEL_SOURCES:
         if sources is None:
             with open(os.path.join(ROOT, rel)) as fh:
                 text = fh.read()
@@ -87,12 +97,14 @@ def kernel_hash(sources=None):
 def measured_traffic(workload):
     """HBM bytes per launch from the committed rocprofv3 --pmc summary, if it
     was taken on the current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", "step_kernel_%s_pmc.json" % workload)
+    binary = workload in BIN_WORKLOADS
+    path = os.path.join(ROOT, "profiles", "%s_%s_pmc.json"
+                        % ("bin_step_kernel" if binary else "step_kernel", workload))
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         d = json.load(fh)
-    if d.get("kernel_source_sha") != kernel_hash():
+    if d.get("kernel_source_sha") != kernel_hash(files=BIN_KERNEL_SOURCES if binary else None):
         return None
     return d.get("hbm_bytes_per_launch")
 
@@ -169,6 +181,119 @@ def cpu_baseline(wl):
             "cpu_model": cpu_model(), "single_thread_mlups": sites / dt1 / 1e6}
 
 
+def make_binary(wl):
+    """lbm_bin_params and the initial (rho, phi) of a binary workload."""
+    from paper_0710_5470_amd import inputs, lbm
+    q, shape = BIN_WORKLOADS[wl]
+    phi = inputs.tanh_drop(shape, shape[0] / 4.0, 1.0, -1.0, 2.0)
+    rho = 1.0 + inputs.uniform_noise(shape, 0.01, 41)
+    return lbm.bin_params(lattice=q, shape=shape, **BIN_PARAMS), rho, phi
+
+
+def cpu_baseline_binary(wl):
+    """The FP64 CPU oracle's binary stepper on a bounded sample of the same
+    workload: a 256 x 256 x 24 slab (D3Q19, 36 steps) or the 1024 x 1024 box
+    (D2Q9, 100 steps), about 10 s on 8 cores."""
+    import numpy as np
+    import oracle
+    from paper_0710_5470_amd import inputs
+    q, shape = BIN_WORKLOADS[wl]
+    sample = (256, 256, 24) if q == 19 else (1024, 1024)
+    phi = inputs.tanh_drop(sample, min(sample) / 3.0, 1.0, -1.0, 2.0)
+    rho = 1.0 + inputs.uniform_noise(sample, 0.01, 41)
+    bp = oracle.bin_params(q=q, shape=sample, **BIN_PARAMS)
+    f, g = oracle.bin_init(bp, rho, phi)
+    steps = 36 if q == 19 else 100
+    cores = oracle.max_threads()
+    t0 = time.perf_counter()
+    f, g = oracle.bin_run(bp, f, g, steps)
+    dt = time.perf_counter() - t0
+    sites = int(np.prod(sample))
+    oracle.set_threads(1)
+    t1 = time.perf_counter()
+    oracle.bin_run(bp, f, g, 1)
+    dt1 = time.perf_counter() - t1
+    oracle.set_threads(cores)
+    return {"value": sites * steps / dt / 1e6, "unit": "MLUPS", "cores": cores, "kind": "oracle",
+            "sample": "%s periodic lattice, same physics, %d steps, FP64 C oracle (%.2f s)"
+                      % ("x".join(map(str, sample)), steps, dt),
+            "cpu_model": cpu_model(), "single_thread_mlups": sites / dt1 / 1e6}
+
+
+def bench_binary(args):
+    """Time the binary-fluid step on a named workload; one JSON line."""
+    import torch
+    from paper_0710_5470_amd import autotune, lbm
+    wl = args.workload
+    q, shape = BIN_WORKLOADS[wl]
+    p, rho, phi = make_binary(wl)
+    sim = lbm.BinarySimulation(p, rho, phi)
+    n = sim.n
+    tuned = False
+    if args.tile >= 0 or args.planes > 0:
+        sim.set_launch(args.tile, args.planes)
+    elif not args.no_tune:
+        autotune.autotune_binary(sim, verbose=True)
+        tuned = True
+    tile, planes, wgs = sim.launch()
+    sim.step(args.warmup)
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    sim.step(args.steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kern_ms = e0.elapsed_time(e1) / args.steps
+    mass, phi_total, mom = sim.invariants()
+    ok = True
+    try:
+        vmax = sim.max_spurious_u()
+    except lbm.LBMError:
+        vmax, ok = float("nan"), False
+    bytes_site = 4 * q * 8  # f and g, each read once and written once, FP64
+    achieved = bytes_site * n / (kern_ms * 1e-3) / 1e9
+    out = {
+        "metric": "MLUPS and HBM GB/s of the binary-fluid step (%s)" % wl,
+        "value": round(n * args.steps / wall / 1e6, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall * 1e3 / args.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": wl, "lattice": "D3Q19" if q == 19 else "D2Q9", "extent": list(shape),
+                   "model": "binary fluid", **BIN_PARAMS,
+                   "init": "phi drop R=%g (tanh width 2) + rho noise 0.01 (seed 41)" % (shape[0] / 4.0),
+                   "launch": {"tile": lbm.lbm_bin_tile_shape(q, tile), "planes_per_workgroup": planes,
+                              "workgroups": wgs, "autotuned": tuned}},
+        "hbm_gbs_algorithmic": round(achieved, 1),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
+                     "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
+                     "traffic": measured_traffic(wl), "bytes_per_site": bytes_site,
+                     "kernel_ms": round(kern_ms, 5)},
+        "state_after": {"finite": ok, "max_vel": vmax, "mass": mass, "phi_total": phi_total,
+                        "momentum": mom},
+    }
+    sim.close()
+    del sim
+    cgbs, cms, cok = copy_ceiling(bytes_site * n // 2)
+    if not cok:
+        raise RuntimeError("stream copy check failed")
+    out["roofline"].update(copy_ceiling_gbs=round(cgbs, 1), frac_of_copy=round(achieved / cgbs, 4),
+                           copy_ms=round(cms, 5))
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline_binary(wl)
+    print(json.dumps(out), flush=True)
+
+
 def copy_calibration(nbytes, reps):
     """The library's streaming copy of nbytes (read nbytes, write nbytes),
     repeated; its FETCH_SIZE / WRITE_SIZE counters scale the LBM kernel's."""
@@ -182,7 +307,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=400)
     ap.add_argument("--warmup", type=int, default=40)
-    ap.add_argument("--workload", default="d3q19_256_fp32_force", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="d3q19_256_fp32_force",
+                    choices=sorted(WORKLOADS) + sorted(BIN_WORKLOADS))
     ap.add_argument("--tile", type=int, default=-1)
     ap.add_argument("--planes", type=int, default=0)
     ap.add_argument("--no-tune", action="store_true")
@@ -203,6 +329,8 @@ def main():
     import torch
     if args.copy_bytes:
         return copy_calibration(args.copy_bytes, args.steps)
+    if args.workload in BIN_WORKLOADS:
+        return bench_binary(args)
     from paper_0710_5470_amd import autotune, inputs, lbm
 
     wl = args.workload

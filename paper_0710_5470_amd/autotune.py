@@ -150,3 +150,37 @@ def autotune_batch(plist, rho0, steps=8, use_cache=True, verbose=False):
         except OSError:
             pass
     return t, c
+
+
+def binary_candidates(lattice, np_):
+    """(tile, planes per workgroup) pairs of the binary-fluid step."""
+    planes = sorted(set(min(c, np_) for c in (8, 16, 32, 64)))
+    return [(t, c) for t in range(lbm.lbm_bin_tile_count(lattice)) for c in planes]
+
+
+def autotune_binary(sim, steps=10, reps=2, verbose=False):
+    """Time every launch shape of a BinarySimulation (its state advances by
+    the timing steps) and apply the fastest.  Returns (tile, planes, ms)."""
+    p = sim.p
+    np_ = p.nz if p.lattice == lbm.D3Q19 else p.ny
+    stream = torch.cuda.current_stream()
+    results = []
+    for t, c in binary_candidates(p.lattice, np_):
+        sim.set_launch(t, c)
+        sim.step(2)
+        best = float("inf")
+        for _ in range(reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            sim.step(steps)
+            e1.record(stream)
+            e1.synchronize()
+            best = min(best, e0.elapsed_time(e1) / steps)
+        results.append((best, t, c))
+        if verbose:
+            print("autotune binary tile %d planes %d: %.4f ms/step" % (t, c, best), file=sys.stderr,
+                  flush=True)
+    ms, t, c = min(results)
+    sim.set_launch(t, c)
+    return t, c, ms

@@ -89,16 +89,22 @@ template <class L> __device__ __forceinline__ double bin_m_terms(const BinCoefs 
     return m;
 }
 
-// Collide both distributions at one site.  fin, gin: populations arriving at
-// the site; phi: sum of gin (formed by the caller in the same order as the
-// stencil's field); d, lap: gradient and Laplacian of phi.  emit_f(i, v) and
-// emit_g(i, v) receive the collided values.
-template <class L, class EF, class EG>
-__device__ __forceinline__ void bin_collide(const BinCoefs &c, const double fin[L::Q], const double gin[L::Q],
-                                            double phi, const double d[3], double lap, EF &&emit_f,
-                                            EG &&emit_g, double *obs = nullptr)
+// Site quantities both collisions need.
+struct BinSite {
+    double rho, u[3], uu, phi, mu;
+};
+
+// Collide f at one site.  fin: populations arriving at the site; phi: the
+// order parameter there (the sum of the arriving g, formed by the caller in
+// the same order as the stencil's field); d, lap: gradient and Laplacian of
+// phi.  emit(i, v) receives each collided value.  Returns what the g
+// collision needs.
+template <class L, class EF>
+__device__ __forceinline__ BinSite bin_collide_f(const BinCoefs &c, const double fin[L::Q], double phi,
+                                                 const double d[3], double lap, EF &&emit)
 {
     constexpr int Q = L::Q, DIM = L::DIM;
+    BinSite s;
     double rho = 0.0, j[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int i = 0; i < Q; i++) {
@@ -108,54 +114,69 @@ __device__ __forceinline__ void bin_collide(const BinCoefs &c, const double fin[
         if (L::ez[i]) j[2] += L::ez[i] * fin[i];
     }
     const double inv = 1.0 / rho;
-    const double u[3] = {j[0] * inv, j[1] * inv, DIM == 3 ? j[2] * inv : 0.0};
-    const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    s.rho = rho;
+    s.u[0] = j[0] * inv;
+    s.u[1] = j[1] * inv;
+    s.u[2] = DIM == 3 ? j[2] * inv : 0.0;
+    s.uu = s.u[0] * s.u[0] + s.u[1] * s.u[1] + s.u[2] * s.u[2];
+    s.phi = phi;
     const double p2 = phi * phi;
     const double p0 = rho * (1.0 / 3.0) + 0.5 * c.pa * p2 + 0.75 * c.pb * p2 * p2;
-    const double mu = c.pa * phi + c.pb * p2 * phi - c.kappa * lap;
-    double M[6] = {c.kappa * d[0] * d[0], c.kappa * d[1] * d[1], c.kappa * d[2] * d[2],
-                   c.kappa * d[0] * d[1], c.kappa * d[1] * d[2], c.kappa * d[2] * d[0]};
-    // per-class terms of f: w^p p0 - (3/2) w rho u^2 / 3 - w^t kappa phi lap
-    const double trX3 = rho * uu * (1.0 / 3.0);
+    s.mu = c.pa * phi + c.pb * p2 * phi - c.kappa * lap;
+    const double M[6] = {c.kappa * d[0] * d[0], c.kappa * d[1] * d[1], c.kappa * d[2] * d[2],
+                         c.kappa * d[0] * d[1], c.kappa * d[1] * d[2], c.kappa * d[2] * d[0]};
+    // per-class terms: w^p p0 - (3/2) w rho u^2 / 3 - w^t kappa phi lap
+    const double trX3 = rho * s.uu * (1.0 / 3.0);
     const double klap = c.kappa * phi * lap;
     const double stc[2] = {c.wp_ax * p0 - 1.5 * c.w_ax * trX3 - c.wt_ax * klap,
                            c.wp_off * p0 - 1.5 * c.w_off * trX3 - c.wt_off * klap};
-    // per-class terms of g: w^p gamma mu - (3/2) w phi u^2 / 3
-    const double gmu = c.gamma * mu;
-    const double gtc[2] = {c.wp_ax * gmu - 0.5 * c.w_ax * phi * uu,
-                           c.wp_off * gmu - 0.5 * c.w_off * phi * uu};
     const double om = c.omega, keep = 1.0 - om;
-    const double omg = c.omega_g, keepg = 1.0 - omg;
-    double sumE = 0.0, sumG = 0.0;
+    double sumE = 0.0;
 #pragma unroll
     for (int i = 1; i < Q; i++) {
         if (opp<L>(i) < i) continue;
         const int o = opp<L>(i);
         const bool axis = nnz<L>(i) == 1;
         const double w = axis ? c.w_ax : c.w_off;
-        const double eu = edot<L>(i, u);
-        // f: even = (3/2) w rho (e.u)^2 + class terms + w^ab terms; odd = w e.j
+        const double eu = edot<L>(i, s.u);
+        // even = (3/2) w rho (e.u)^2 + class terms + w^ab terms; odd = w e.j
         const double even = 1.5 * w * rho * eu * eu + stc[axis ? 0 : 1] + bin_m_terms<L>(c, M, i);
         const double odd = w * edot<L>(i, j);
         sumE += even;
-        emit_f(i, keep * fin[i] + om * (even + odd));
-        emit_f(o, keep * fin[o] + om * (even - odd));
-        // g: even = (3/2) w phi (e.u)^2 + class terms; odd = w phi e.u
-        const double geven = 1.5 * w * phi * eu * eu + gtc[axis ? 0 : 1];
-        const double godd = w * phi * eu;
-        sumG += geven;
-        emit_g(i, keepg * gin[i] + omg * (geven + godd));
-        emit_g(o, keepg * gin[o] + omg * (geven - godd));
+        emit(i, keep * fin[i] + om * (even + odd));
+        emit(o, keep * fin[o] + om * (even - odd));
     }
-    emit_f(0, keep * fin[0] + om * (rho - 2.0 * sumE));
-    emit_g(0, keepg * gin[0] + omg * (phi - 2.0 * sumG));
-    if (obs) {
-        obs[0] = rho;
-        obs[1] = u[0];
-        obs[2] = u[1];
-        obs[3] = u[2];
-        obs[4] = mu;
+    emit(0, keep * fin[0] + om * (rho - 2.0 * sumE));
+    return s;
+}
+
+// Collide g at one site with the site quantities of the f collision.
+template <class L, class EG>
+__device__ __forceinline__ void bin_collide_g(const BinCoefs &c, const double gin[L::Q], const BinSite &s,
+                                              EG &&emit)
+{
+    constexpr int Q = L::Q;
+    // per-class terms: w^p gamma mu - (3/2) w phi u^2 / 3
+    const double gmu = c.gamma * s.mu;
+    const double gtc[2] = {c.wp_ax * gmu - 0.5 * c.w_ax * s.phi * s.uu,
+                           c.wp_off * gmu - 0.5 * c.w_off * s.phi * s.uu};
+    const double om = c.omega_g, keep = 1.0 - om;
+    double sumG = 0.0;
+#pragma unroll
+    for (int i = 1; i < Q; i++) {
+        if (opp<L>(i) < i) continue;
+        const int o = opp<L>(i);
+        const bool axis = nnz<L>(i) == 1;
+        const double w = axis ? c.w_ax : c.w_off;
+        const double eu = edot<L>(i, s.u);
+        // even = (3/2) w phi (e.u)^2 + class terms; odd = w phi e.u
+        const double even = 1.5 * w * s.phi * eu * eu + gtc[axis ? 0 : 1];
+        const double odd = w * s.phi * eu;
+        sumG += even;
+        emit(i, keep * gin[i] + om * (even + odd));
+        emit(o, keep * gin[o] + om * (even - odd));
     }
+    emit(0, keep * gin[0] + om * (s.phi - 2.0 * sumG));
 }
 
 // Wrapped coordinates of a column: value, value - 1, value + 1.
@@ -179,7 +200,13 @@ __global__ __launch_bounds__(TX * TY) void bin_step_kernel(BinArgs a)
     __shared__ double ring[4][PL];
 
     const int tid = threadIdx.x;
+    // Workgroup ids are dealt to the XCDs round-robin.  D2Q9: give each XCD
+    // a contiguous run of rows instead, so the rows a workgroup's halo reads
+    // are fetched under the same L2 (measured faster).  D3Q19 keeps the
+    // round-robin order: the contiguous order fetches fewer bytes but runs
+    // slower there.
     int b = blockIdx.x;
+    if (L::DIM == 2 && (gridDim.x & 7) == 0) b = (b & 7) * (gridDim.x >> 3) + (b >> 3);
     const int bx = b % a.tiles_x;
     b /= a.tiles_x;
     const int by = b % a.tiles_y;
@@ -189,32 +216,49 @@ __global__ __launch_bounds__(TX * TY) void bin_step_kernel(BinArgs a)
     const int p_end = min(p_begin + a.cp, a.np);
     const long long nxy = (long long)a.nx * a.ny;
 
-    // ring entries this thread forms: wrapped in-plane coordinates
-    int rx[NIT][3], ry[NIT][3];
-    bool rv[NIT];
-#pragma unroll
-    for (int k = 0; k < NIT; k++) {
-        const int e = tid + k * NT;
-        rv[k] = e < PL;
-        const int lx = e % PW - 1, ly = e / PW - HY;
-        wrap3(x0 + lx, a.nx, rx[k]);
-        wrap3(y0 + ly, a.ny, ry[k]);
-    }
     // own site
     const int tx = tid % TX, ty = tid / TX;
     const int x = x0 + tx, y = y0 + ty;
     const bool own = x < a.nx && y < a.ny;
-    int ox3[3], oy3[3];
-    wrap3(x, a.nx, ox3);
-    wrap3(y, a.ny, oy3);
     const int c_own = (ty + HY) * PW + tx + 1;
+    // Ring entries this thread forms: its own site first (k = 0), so the g
+    // it sums for phi of the plane ahead are the ones it collides there one
+    // plane later, then halo entries h = tid + (k - 1) NT: the rows below
+    // and above the tile (3D), then its left and right columns.
+    constexpr int H = PL - NT;
+    int rx[NIT][3], ry[NIT][3], re[NIT];
+    bool rv[NIT];
+#pragma unroll
+    for (int k = 0; k < NIT; k++) {
+        int lx, ly;
+        if (k == 0) {
+            lx = tx;
+            ly = ty;
+            rv[k] = true;
+        } else {
+            const int h = tid + (k - 1) * NT;
+            rv[k] = h < H;
+            if (L::DIM == 3 && h < 2 * PW) {
+                lx = h % PW - 1;
+                ly = h < PW ? -1 : TY;
+            } else {
+                const int h2 = L::DIM == 3 ? h - 2 * PW : h;
+                lx = (h2 & 1) ? TX : -1;
+                ly = h2 >> 1;
+            }
+        }
+        re[k] = (ly + HY) * PW + lx + 1;
+        wrap3(x0 + lx, a.nx, rx[k]);
+        wrap3(y0 + ly, a.ny, ry[k]);
+    }
 
     auto src_index = [&](const int (&X)[3], const int (&Y)[3], const int (&P)[3], int i) {
         return (long long)i * a.stride + (long long)from3(P, op<L>(i)) * nxy +
                (long long)from3(Y, oy<L>(i)) * a.nx + from3(X, ox<L>(i));
     };
-    // phi of plane p for every ring entry, into ring slot s
-    auto form_phi = [&](int p, int s) {
+    // phi of plane p for every ring entry, into ring slot s; the own site's
+    // arriving g into gown
+    auto form_phi = [&](int p, int s, double (&gown)[Q]) {
         int P[3];
         wrap3(p, a.np, P);
 #pragma unroll
@@ -222,44 +266,50 @@ __global__ __launch_bounds__(TX * TY) void bin_step_kernel(BinArgs a)
             if (!rv[k]) continue;
             double v = 0.0;
 #pragma unroll
-            for (int i = 0; i < Q; i++) v += a.gsrc[src_index(rx[k], ry[k], P, i)];
-            ring[s][tid + k * NT] = v;
+            for (int i = 0; i < Q; i++) {
+                const double gi = a.gsrc[src_index(rx[k], ry[k], P, i)];
+                if (k == 0) gown[i] = gi;
+                v += gi;
+            }
+            ring[s][re[k]] = v;
         }
     };
 
-    form_phi(p_begin - 1, 0);
-    form_phi(p_begin, 1);
+    double gcur[Q], gnext[Q];
+    form_phi(p_begin - 1, 0, gnext);
+    form_phi(p_begin, 1, gcur);
     for (int t = 0; p_begin + t < p_end; t++) {
-        form_phi(p_begin + t + 1, (t + 2) & 3);
+        form_phi(p_begin + t + 1, (t + 2) & 3, gnext);
         __syncthreads();
-        if (!own) continue;
-        const int p = p_begin + t;
-        const double *sl[3] = {ring[t & 3], ring[(t + 1) & 3], ring[(t + 2) & 3]};
-        const double phi = sl[1][c_own];
-        double d[3] = {0.0, 0.0, 0.0}, lap = 0.0;
+        if (own) {
+            const int p = p_begin + t;
+            const double *sl[3] = {ring[t & 3], ring[(t + 1) & 3], ring[(t + 2) & 3]};
+            const double phi = sl[1][c_own];
+            double d[3] = {0.0, 0.0, 0.0}, lap = 0.0;
 #pragma unroll
-        for (int i = 1; i < Q; i++) {
-            const double v = sl[1 + op<L>(i)][c_own + oy<L>(i) * PW + ox<L>(i)];
-            const double g = bin_grad_coef<L>(a.c, i) * v;
-            if (L::ex[i]) d[0] += L::ex[i] * g;
-            if (L::ey[i]) d[1] += L::ey[i] * g;
-            if (L::ez[i]) d[2] += L::ez[i] * g;
-            lap += bin_lap_coef<L>(a.c, i) * (v - phi);
-        }
-        int P[3];
-        wrap3(p, a.np, P);
-        double fin[Q], gin[Q];
+            for (int i = 1; i < Q; i++) {
+                const double v = sl[1 + op<L>(i)][c_own + oy<L>(i) * PW + ox<L>(i)];
+                const double g = bin_grad_coef<L>(a.c, i) * v;
+                if (L::ex[i]) d[0] += L::ex[i] * g;
+                if (L::ey[i]) d[1] += L::ey[i] * g;
+                if (L::ez[i]) d[2] += L::ez[i] * g;
+                lap += bin_lap_coef<L>(a.c, i) * (v - phi);
+            }
+            int P[3];
+            wrap3(p, a.np, P);
+            const long long site = (long long)p * nxy + (long long)y * a.nx + x;
+            double fin[Q];
 #pragma unroll
-        for (int i = 0; i < Q; i++) {
-            const long long s = src_index(ox3, oy3, P, i);
-            fin[i] = a.fsrc[s];
-            gin[i] = a.gsrc[s];
+            for (int i = 0; i < Q; i++) fin[i] = a.fsrc[src_index(rx[0], ry[0], P, i)];
+            const BinSite st = bin_collide_f<L>(a.c, fin, phi, d, lap, [&](int i, double v) {
+                __builtin_nontemporal_store(v, a.fdst + (long long)i * a.stride + site);
+            });
+            bin_collide_g<L>(a.c, gcur, st, [&](int i, double v) {
+                __builtin_nontemporal_store(v, a.gdst + (long long)i * a.stride + site);
+            });
         }
-        const long long site = (long long)p * nxy + (long long)y * a.nx + x;
-        bin_collide<L>(
-            a.c, fin, gin, phi, d, lap,
-            [&](int i, double v) { __builtin_nontemporal_store(v, a.fdst + (long long)i * a.stride + site); },
-            [&](int i, double v) { __builtin_nontemporal_store(v, a.gdst + (long long)i * a.stride + site); });
+#pragma unroll
+        for (int i = 0; i < Q; i++) gcur[i] = gnext[i];
     }
 }
 
@@ -312,10 +362,12 @@ __global__ void bin_init_kernel(Geom g, BinCoefs c, const double *__restrict__ r
         fin[1 + 2 * a] += half;
         fin[2 + 2 * a] -= half;
     }
-    bin_collide<L>(
-        ce, fin, gin, phi, d, lap,
-        [&](int i, double v) { fdst[(long long)i * g.stride + neighbour<L>(g, x, y, p, i, -1)] = v; },
-        [&](int i, double v) { gdst[(long long)i * g.stride + neighbour<L>(g, x, y, p, i, -1)] = v; });
+    const BinSite st = bin_collide_f<L>(ce, fin, phi, d, lap, [&](int i, double v) {
+        fdst[(long long)i * g.stride + neighbour<L>(g, x, y, p, i, -1)] = v;
+    });
+    bin_collide_g<L>(ce, gin, st, [&](int i, double v) {
+        gdst[(long long)i * g.stride + neighbour<L>(g, x, y, p, i, -1)] = v;
+    });
 }
 
 // Observables of the pulled state: rho, phi, u = j / rho (for mu, a second

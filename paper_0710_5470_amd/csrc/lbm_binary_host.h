@@ -24,7 +24,7 @@ namespace {
 
 // launch shapes: D2Q9 rows of tx sites; D3Q19 tx x ty in-plane tiles
 constexpr TileShape BIN_TILES_2D[] = {{128, 1}, {256, 1}};
-constexpr TileShape BIN_TILES_3D[] = {{32, 8}, {64, 4}, {64, 8}};
+constexpr TileShape BIN_TILES_3D[] = {{32, 8}, {64, 4}, {64, 8}, {128, 4}};
 constexpr int BNT2 = sizeof(BIN_TILES_2D) / sizeof(BIN_TILES_2D[0]);
 constexpr int BNT3 = sizeof(BIN_TILES_3D) / sizeof(BIN_TILES_3D[0]);
 
@@ -103,14 +103,15 @@ void bin_grid(const lbm_bin_ctx *c, int tile, int cp, int &tx_n, int &ty_n, int 
     chunks = (c->np + cp - 1) / cp;
 }
 
-// planes per workgroup: enough chunks for about 2048 workgroups, but at
-// least 8 planes each (every chunk forms phi on two extra planes first)
+// planes per workgroup: enough chunks for about 1024 (D2Q9) or 512 (D3Q19)
+// workgroups, but at least 8 planes each (every chunk forms phi on two
+// extra planes first)
 int bin_default_planes(const lbm_bin_ctx *c, int tile)
 {
     int a, b, ch;
     bin_grid(c, tile, c->np, a, b, ch);
-    long long tiles = (long long)a * b;
-    long long want = std::max<long long>(1, std::min<long long>(c->np, (2048 + tiles - 1) / tiles));
+    const long long tiles = (long long)a * b, target = c->p.lattice == LBM_D2Q9 ? 1024 : 512;
+    long long want = std::max<long long>(1, std::min<long long>(c->np, (target + tiles - 1) / tiles));
     return std::min(c->np, std::max(8, (int)((c->np + want - 1) / want)));
 }
 
@@ -141,7 +142,8 @@ void bin_launch_step(lbm_bin_ctx *c)
     } else {
         if (c->tile == 0) bin_launch_t<D3Q19, 32, 8>(c, a, nblk);
         else if (c->tile == 1) bin_launch_t<D3Q19, 64, 4>(c, a, nblk);
-        else bin_launch_t<D3Q19, 64, 8>(c, a, nblk);
+        else if (c->tile == 2) bin_launch_t<D3Q19, 64, 8>(c, a, nblk);
+        else bin_launch_t<D3Q19, 128, 4>(c, a, nblk);
     }
 }
 
@@ -271,7 +273,7 @@ int lbm_bin_init(lbm_bin_ctx **out, const lbm_bin_params *p, void *dev_workspace
         c->nx = p->nx; c->ny = p->ny; c->np = p->nz;
     }
     c->n = (long long)p->nx * p->ny * p->nz;
-    c->tile = p->tile >= 0 ? p->tile : (p->lattice == LBM_D2Q9 ? 1 : 0);
+    c->tile = p->tile >= 0 ? p->tile : (p->lattice == LBM_D2Q9 ? 0 : 3);
     c->cp = p->planes_per_block > 0 ? std::min(p->planes_per_block, c->np) : bin_default_planes(c, c->tile);
     c->c = bin_coefs(p);
     // the initial fields must be finite with rho > 0

@@ -177,12 +177,12 @@ FULL = [("d3q19_256_fp64_binary", 19, (256, 256, 256)), ("d2q9_1024_fp64_binary"
 
 @pytest.mark.parametrize("name,q,shape", FULL)
 def test_full_size_binary_matches_oracle_on_sampled_sites(name, q, shape):
-    """The benchmark's lattices in its default launch: after one step the
-    populations arriving from 512 sampled sites equal the oracle's
-    site-local collision there; the state stays finite and conserves its
-    totals over 50 further steps."""
+    """The benchmark's lattices in the launch the benchmark times (the
+    autotuned one): after one step the populations arriving from 512
+    sampled sites equal the oracle's site-local collision there; the state
+    stays finite and conserves its totals over 50 further steps."""
     import oracle
-    from paper_0710_5470_amd import inputs
+    from paper_0710_5470_amd import autotune, inputs
     lbm = _lbm()
     gp, op = _pair(q, shape)
     n = int(np.prod(shape))
@@ -191,6 +191,8 @@ def test_full_size_binary_matches_oracle_on_sampled_sites(name, q, shape):
     rho = 1.0 + inputs.uniform_noise(shape, 0.01, 41).reshape(-1)
     _say("full-size binary", name)
     sim = lbm.BinarySimulation(gp, rho, phi)
+    tile, planes, ms = autotune.autotune_binary(sim)
+    _say("autotuned launch", tile, planes, "%.4f ms" % ms)
     f0, g0 = [t.cpu().numpy() for t in sim.get_state()]
     sim.step(1)
     f1, g1 = [t.cpu().numpy() for t in sim.get_state()]
