@@ -402,12 +402,18 @@ typedef struct {
     double tau, tau_phi;  /* relaxation times of f and g, Eq. (latbolt); > 1/2     */
     int lattice;          /* LBM_D2Q9 or LBM_D3Q19                                 */
     int nx, ny, nz;       /* lattice extent; nz = 1 for D2Q9                       */
+    /* Stencil and weight overrides as in lbm_params (NaN = the paper's
+     * optimum): B, D the gradient and Laplacian off-axis coefficients;
+     * wp_diag, wt_diag, wxx_diag the D2Q9 weights w^p_5-8, w^t_5-8,
+     * w^xx_5-8 (NaN for D3Q19).  The gamma mu term of g uses the same w^p. */
+    double B, D;
+    double wp_diag, wt_diag, wxx_diag;
     int tile;             /* launch shape id (lbm_bin_tile_count); -1 = default    */
     int planes_per_block; /* planes marched by one workgroup; <= 0 = default       */
 } lbm_bin_params;
 
 /* phi_a = -0.02, phi_b = 0.02, kappa = 0.04, gamma = 1, tau = tau_phi = 1,
- * D2Q9 100 x 100, default launch. */
+ * D2Q9 100 x 100, every override NaN, default launch. */
 void lbm_bin_params_default(lbm_bin_params *p);
 
 /* Bytes of device workspace (four population buffers, observation fields,

@@ -44,6 +44,11 @@ bool bin_valid(const lbm_bin_params *p)
     if (!(p->kappa >= 0.0) || !std::isfinite(p->kappa)) return false;
     if (!(p->gamma >= 0.0) || !std::isfinite(p->gamma)) return false;
     if (p->tile >= bin_tile_count(p->lattice)) return false;
+    if (p->lattice == LBM_D3Q19 &&
+        (!std::isnan(p->wp_diag) || !std::isnan(p->wt_diag) || !std::isnan(p->wxx_diag)))
+        return false;
+    for (double v : {p->B, p->D, p->wp_diag, p->wt_diag, p->wxx_diag})
+        if (std::isinf(v)) return false;
     return true;
 }
 
@@ -69,7 +74,7 @@ double *bin_f(lbm_bin_ctx *c, int which) { return bws(c, which ? c->o_fb : c->o_
 double *bin_g(lbm_bin_ctx *c, int which) { return bws(c, which ? c->o_gb : c->o_ga); }
 
 // Stencils of Eqs. (xderiv), (laplace), (laplacian3d) and the equilibrium
-// weights (summary / Eq. (3dres)) at the paper's optimum.
+// weights (summary / Eq. (3dres)): the paper's optimum unless overridden.
 BinCoefs bin_coefs(const lbm_bin_params *p)
 {
     lbm_params q;
@@ -77,6 +82,11 @@ BinCoefs bin_coefs(const lbm_bin_params *p)
     q.lattice = p->lattice;
     q.kappa = p->kappa;
     q.tau = p->tau;
+    q.B = p->B;
+    q.D = p->D;
+    q.wp_diag = p->wp_diag;
+    q.wt_diag = p->wt_diag;
+    q.wxx_diag = p->wxx_diag;
     const Coefs<double> k = make_coefs(&q);
     BinCoefs c{};
     c.A = k.A; c.B = k.B; c.C = k.C; c.D = k.D;
@@ -236,6 +246,8 @@ void lbm_bin_params_default(lbm_bin_params *p)
     p->nx = 100;
     p->ny = 100;
     p->nz = 1;
+    p->B = p->D = NAN;
+    p->wp_diag = p->wt_diag = p->wxx_diag = NAN;
     p->tile = -1;
     p->planes_per_block = 0;
 }
