@@ -730,7 +730,77 @@ typedef struct {
     double phi_a, phi_b; /* bulk free energy phi_a phi^2/2 + phi_b phi^4/4 */
     double gamma;        /* mobility coefficient of the mu term */
     double tau_phi;      /* relaxation time of g */
+    int wall;            /* 1: walls at both ends of the last axis (see below) */
 } orc_bin_params;
+
+/* Walls (not defined by the paper; the forcing section only remarks that
+ * boundaries are harder with forcing).  With wall = 1 the last axis (z for
+ * D3Q19, y for D2Q9) is bounded by two walls halfway between lattice planes,
+ * at -1/2 and n - 1/2: a population streaming into a wall returns to the
+ * site it left with its velocity reversed (halfway bounce-back), and the
+ * stencils read a site beyond a wall as its mirror image in the fluid (zero
+ * normal derivative of phi: a neutral wall).  The other axes stay periodic. */
+static long bin_sidx(const orc_bin_params *bp, int x, int y, int z)
+{
+    const orc_params *p = &bp->base;
+    if (bp->wall) {
+        if (p->q == 19) {
+            if (z < 0) z = -1 - z;
+            else if (z >= p->nz) z = 2 * p->nz - 1 - z;
+        } else {
+            if (y < 0) y = -1 - y;
+            else if (y >= p->ny) y = 2 * p->ny - 1 - y;
+        }
+    }
+    return sidx(p, x, y, z);
+}
+
+/* 1 if site (x, y, z) lies beyond a wall */
+static int bin_beyond(const orc_bin_params *bp, int y, int z)
+{
+    const orc_params *p = &bp->base;
+    if (!bp->wall) return 0;
+    return p->q == 19 ? (z < 0 || z >= p->nz) : (y < 0 || y >= p->ny);
+}
+
+static int opposite(const tables *t, int i)
+{
+    for (int j = 0; j < t->q; j++)
+        if (t->e[j][0] == -t->e[i][0] && t->e[j][1] == -t->e[i][1] && t->e[j][2] == -t->e[i][2])
+            return j;
+    return -1;
+}
+
+/* gradient and Laplacian of phi with the stencils, walls mirrored */
+static void bin_derivatives(const orc_bin_params *bp, const tables *t, const double *phi,
+                            double *grad, double *lap)
+{
+    const orc_params *p = &bp->base;
+    long n = nsites(p);
+    const double(*st[4])[3][3] = {t->gx, t->gy, t->gz, t->lap};
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int z = 0; z < p->nz; z++)
+        for (int y = 0; y < p->ny; y++)
+            for (int x = 0; x < p->nx; x++) {
+                long s = sidx(p, x, y, z);
+                double v[4];
+                for (int k = 0; k < 4; k++) {
+                    double acc = 0.0;
+                    for (int sl = 0; sl < 3; sl++)
+                        for (int r = 0; r < 3; r++)
+                            for (int c = 0; c < 3; c++) {
+                                double kc = st[k][sl][r][c];
+                                if (kc == 0.0) continue;
+                                acc += kc * phi[bin_sidx(bp, x + c - 1, y + 1 - r, z + 1 - sl)];
+                            }
+                    v[k] = acc;
+                }
+                grad[s] = v[0];
+                grad[n + s] = v[1];
+                grad[2 * n + s] = (t->dim == 3) ? v[2] : 0.0;
+                lap[s] = v[3];
+            }
+}
 
 static double bin_p0(const orc_bin_params *bp, double rho, double phi)
 {
@@ -822,7 +892,7 @@ int orc_bin_init(const orc_bin_params *bp, const double *rho0, const double *phi
     long n = nsites(p);
     double *grad = (double *)malloc(sizeof(double) * 3 * n);
     double *lap = (double *)malloc(sizeof(double) * n);
-    derivatives(p, &t, phi0, grad, lap);
+    bin_derivatives(bp, &t, phi0, grad, lap);
 #pragma omp parallel for schedule(static)
     for (long s = 0; s < n; s++) {
         double u[3] = {0, 0, 0}, j[3];
@@ -864,7 +934,7 @@ int orc_bin_run(const orc_bin_params *bp, double *f, double *g, int nsteps)
     for (int step = 0; step < nsteps; step++) {
         moments(p, &t, fc, rho, j);
         order_parameter(p, &t, gc, phi);
-        derivatives(p, &t, phi, grad, lap);
+        bin_derivatives(bp, &t, phi, grad, lap);
 #pragma omp parallel for collapse(2) schedule(static)
         for (int z = 0; z < p->nz; z++)
             for (int y = 0; y < p->ny; y++)
@@ -878,7 +948,10 @@ int orc_bin_run(const orc_bin_params *bp, double *f, double *g, int nsteps)
                     geq_bin_site_t(bp, &t, phi[s], u, bin_mu(bp, phi[s], lap[s]), ge);
                     for (int i = 0; i < q; i++) {
                         const int *e = t.e[i];
-                        long dst = i * n + sidx(p, x + e[0], y + e[1], z + e[2]);
+                        /* into a wall: back to this site, reversed */
+                        long dst = bin_beyond(bp, y + e[1], z + e[2])
+                                       ? (long)opposite(&t, i) * n + s
+                                       : i * n + sidx(p, x + e[0], y + e[1], z + e[2]);
                         double fi = fc[i * n + s], gi = gc[i * n + s];
                         fn[dst] = fi - (fi - fe[i]) / p->tau;
                         gn[dst] = gi - (gi - ge[i]) / bp->tau_phi;
@@ -911,7 +984,7 @@ int orc_bin_observe(const orc_bin_params *bp, const double *f, const double *g, 
     double *lap = (double *)malloc(sizeof(double) * n);
     moments(p, &t, f, r, j);
     order_parameter(p, &t, g, ph);
-    derivatives(p, &t, ph, grad, lap);
+    bin_derivatives(bp, &t, ph, grad, lap);
     for (long s = 0; s < n; s++) {
         if (rho) rho[s] = r[s];
         if (phi) phi[s] = ph[s];
@@ -962,7 +1035,7 @@ void orc_bin_geq_site(const orc_bin_params *bp, double phi, const double *u, dou
 int orc_bin_collide_sites(const orc_bin_params *bp, const double *f, const double *g, int nsite,
                           const int *xyz, double *fout, double *gout)
 {
-    if (!bin_valid(bp)) return -1;
+    if (!bin_valid(bp) || bp->wall) return -1; /* periodic lattices only */
     const orc_params *p = &bp->base;
     tables t;
     build_tables(p, &t);

@@ -289,3 +289,104 @@ def test_site_local_collision_matches_the_stepper(q, shape):
             + (xyz[:, 0] + e[i, 0]) % nx
         np.testing.assert_allclose(f1[i, dst], fo[:, i], rtol=0, atol=1e-15)
         np.testing.assert_allclose(g1[i, dst], go[:, i], rtol=0, atol=1e-15)
+
+
+# ---- walls (halfway bounce-back, mirrored stencils) --------------------------
+
+@pytest.mark.parametrize("q,shape", [(9, (2, 32)), (19, (2, 2, 32))])
+def test_walls_shear_mode_decays_with_viscosity(q, shape):
+    """Between two halfway bounce-back walls (at -1/2 and n - 1/2 on the last
+    axis) the no-slip shear mode u_x = U sin(pi (z + 1/2) / n) decays at
+    nu (pi / n)^2, nu = (tau - 1/2) / 3."""
+    nz, tau = shape[-1], 0.8
+    rows = int(np.prod(shape)) // nz
+    bp = O.bin_params(q=q, shape=shape, phi_a=PA, phi_b=PB, kappa=KAPPA, tau=tau, wall=1)
+    prof = np.sin(np.pi * (np.arange(nz) + 0.5) / nz)
+    u0 = np.zeros((3, rows * nz))
+    u0[0] = np.repeat(1e-3 * prof, rows)
+    f, g = O.bin_init(bp, np.ones(rows * nz), np.ones(rows * nz), u0)
+    amps = []
+    for steps in (200, 1200):
+        v = O.bin_observe(bp, *O.bin_run(bp, f, g, steps))[2][0].reshape(nz, rows)[:, 0]
+        amps.append(2 * np.mean(v * prof))
+    want = (tau - 0.5) / 3 * (np.pi / nz) ** 2
+    assert abs(np.log(amps[0] / amps[1]) / 1000 / want - 1) < 2e-3
+
+
+@pytest.mark.parametrize("q,shape", [(9, (9, 14)), (19, (5, 6, 9))])
+def test_walls_conserve_mass_and_order_parameter(q, shape):
+    bp = O.bin_params(q=q, shape=shape, phi_a=PA, phi_b=PB, kappa=KAPPA, tau=0.8, tau_phi=1.2,
+                      gamma=0.9, wall=1)
+    rng = np.random.default_rng(16)
+    n = int(np.prod(shape))
+    u0 = 0.02 * rng.standard_normal((3, n))
+    if q == 9:
+        u0[2] = 0
+    f, g = O.bin_init(bp, 1 + 0.02 * rng.standard_normal(n), 0.9 * np.tanh(rng.standard_normal(n)),
+                      u0)
+    m0, p0, _ = O.bin_totals(bp, f, g)
+    f, g = O.bin_run(bp, f, g, 300)
+    m1, p1, _ = O.bin_totals(bp, f, g)
+    assert np.isfinite(f).all() and np.isfinite(g).all()
+    assert abs(m1 - m0) < 1e-12 * n and abs(p1 - p0) < 1e-12 * n
+
+
+def discrete_profile_neumann(phi_init, total, kappa=KAPPA):
+    """As discrete_profile, with mirrored ends (phi_{-1} = phi_0,
+    phi_n = phi_{n-1}) instead of periodic ones."""
+    n = phi_init.size
+    phi, mu0 = phi_init.astype(float).copy(), 0.0
+    idx = np.arange(n)
+    up, dn = np.minimum(idx + 1, n - 1), np.maximum(idx - 1, 0)
+    for _ in range(60):
+        lap = phi[up] + phi[dn] - 2 * phi
+        res = np.concatenate([_dpsi(phi) - kappa * lap - mu0, [phi.sum() - total]])
+        J = np.zeros((n + 1, n + 1))
+        J[idx, idx] += PA + 3 * PB * phi ** 2 + 2 * kappa
+        np.add.at(J, (idx, up), -kappa)
+        np.add.at(J, (idx, dn), -kappa)
+        J[:n, n] = -1
+        J[n, :n] = 1
+        d = np.linalg.solve(J, -res)
+        phi += d[:n]
+        mu0 += d[n]
+        if np.abs(d).max() < 1e-15:
+            break
+    return phi, mu0
+
+
+@pytest.mark.parametrize("q", [9, 19])
+def test_walls_flat_interface_relaxes_to_the_discrete_neumann_steady_state(q):
+    """One interface parallel to the walls relaxes to the solution of
+    psi'(phi) - kappa lap_h(phi) = mu_0 with mirrored ends: the mirrored
+    stencils make the walls neutral (no wetting), at rest."""
+    nz = 48
+    shape = (2, 2, nz) if q == 19 else (2, nz)
+    rows = int(np.prod(shape)) // nz
+    bp = O.bin_params(q=q, shape=shape, phi_a=PA, phi_b=PB, kappa=KAPPA, wall=1)
+    prof = np.tanh((np.arange(nz) - (nz - 1) / 2) / 2.0)
+    f, g = O.bin_init(bp, np.ones(rows * nz), np.repeat(prof, rows))
+    ref, mu0 = discrete_profile_neumann(prof, O.bin_totals(bp, f, g)[1] / rows)
+    # the bulk relaxes by diffusion across the channel (about 12x per 30,000 steps)
+    f, g = O.bin_run(bp, f, g, 90000)
+    r, ph, v, mu = O.bin_observe(bp, f, g)
+    assert np.abs(ph.reshape(nz, rows)[:, 0] - ref).max() < 1e-6
+    assert mu.max() - mu.min() < 1e-7
+    assert np.abs(v).max() < 1e-10
+
+
+@pytest.mark.parametrize("q,shape", [(9, (3, 12)), (19, (3, 2, 12))])
+def test_walls_mirror_the_stencils_about_the_halfway_plane(q, shape):
+    """phi = A cos(pi (z + 1/2) / n) is symmetric about both halfway walls,
+    so with the mirrored stencils its Laplacian is the second difference's
+    eigenvalue -(2 - 2 cos(pi / n)) phi at every site, the wall layers
+    included (the axis and diagonal coefficients of Eqs. (laplace) and
+    (laplacian3d) sum to 1 along one axis); mu follows exactly."""
+    nz = shape[-1]
+    rows = int(np.prod(shape)) // nz
+    bp = O.bin_params(q=q, shape=shape, phi_a=PA, phi_b=PB, kappa=KAPPA, wall=1)
+    phi = 0.3 * np.cos(np.pi * (np.arange(nz) + 0.5) / nz)
+    f, g = O.bin_init(bp, np.ones(rows * nz), np.repeat(phi, rows))
+    mu = O.bin_observe(bp, f, g)[3].reshape(nz, rows)[:, 0]
+    want = _dpsi(phi) + KAPPA * (2 - 2 * np.cos(np.pi / nz)) * phi
+    np.testing.assert_allclose(mu, want, rtol=0, atol=1e-15)
