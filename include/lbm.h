@@ -402,6 +402,13 @@ typedef struct {
     double tau, tau_phi;  /* relaxation times of f and g, Eq. (latbolt); > 1/2     */
     int lattice;          /* LBM_D2Q9 or LBM_D3Q19                                 */
     int nx, ny, nz;       /* lattice extent; nz = 1 for D2Q9                       */
+    /* 0: periodic.  1: walls at both ends of the marching axis (y for D2Q9,
+     * z for D3Q19), halfway between planes (at -1/2 and n - 1/2): a
+     * population streaming into a wall returns to its site reversed
+     * (halfway bounce-back, no slip) and the stencils mirror phi about the
+     * wall (zero normal derivative, a neutral wall).  The paper defines no
+     * walls; the forcing section only notes they are harder with forcing. */
+    int wall;
     /* Stencil and weight overrides as in lbm_params (NaN = the paper's
      * optimum): B, D the gradient and Laplacian off-axis coefficients;
      * wp_diag, wt_diag, wxx_diag the D2Q9 weights w^p_5-8, w^t_5-8,
@@ -413,7 +420,7 @@ typedef struct {
 } lbm_bin_params;
 
 /* phi_a = -0.02, phi_b = 0.02, kappa = 0.04, gamma = 1, tau = tau_phi = 1,
- * D2Q9 100 x 100, every override NaN, default launch. */
+ * D2Q9 100 x 100, periodic, every override NaN, default launch. */
 void lbm_bin_params_default(lbm_bin_params *p);
 
 /* Bytes of device workspace (four population buffers, observation fields,
@@ -443,8 +450,8 @@ int lbm_bin_moments(lbm_bin_ctx *ctx, double *dev_rho, double *dev_phi, double *
  * state holds a non-finite value or rho <= 0.  Synchronises. */
 int lbm_bin_max_spurious_u(lbm_bin_ctx *ctx, double *host_out);
 
-/* FP64 totals: mass sum f, order parameter sum g and momentum sum f e
- * (host_mom[3]).  Synchronises. */
+/* FP64 totals of the post-streaming state: mass sum f, order parameter
+ * sum g and momentum sum f e (host_mom[3]).  Synchronises. */
 int lbm_bin_invariants(lbm_bin_ctx *ctx, double *host_mass, double *host_phi, double *host_mom);
 
 /* Copy out / replace the state as post-streaming populations f_i(r,t),

@@ -23,15 +23,23 @@
 // holds the post-collision population of direction i at its source site,
 // and the population arriving at r is S[i][r - e_i].
 //
+// Walls (optional; the paper defines none): two walls halfway between
+// planes at both ends of the marching axis (y for D2Q9, z for D3Q19), the
+// other axes periodic.  A population whose source r - e_i lies beyond a wall
+// is the one that left r towards the wall, reversed (halfway bounce-back):
+// in the pull layout it is read from S[opp(i)][r], an entry no other site
+// reads.  The stencils read a plane beyond a wall as its mirror image in the
+// fluid (zero normal derivative of phi: a neutral wall).
+//
 // March.  A workgroup owns an in-plane tile of TX x TY sites (TY = 1 for
 // D2Q9, whose "planes" are rows) and a chunk of consecutive planes.  Per
 // plane it (1) forms phi = sum_i g_i of the plane ahead, for the tile and a
 // one-site in-plane halo, into an LDS ring of four planes, then (2) after
 // one barrier collides the current plane: the stencils read the ring, the
-// own-site f_i and g_i are pulled again (the g values were fetched one plane
-// earlier, so they come from L2) and the collided values are stored at the
-// site itself, aligned.  With four ring slots the plane being formed is
-// never one still being read, so one barrier per plane suffices.
+// own-site f_i are pulled, the own-site g_i are the ones the thread summed
+// for phi one plane earlier (kept in registers), and the collided values are
+// stored at the site itself, aligned.  With four ring slots the plane being
+// formed is never one still being read, so one barrier per plane suffices.
 #pragma once
 
 #include "lbm_aux.h"
@@ -190,7 +198,7 @@ __device__ __forceinline__ void wrap3(int v, int n, int (&w)[3])
 // the coordinate a population of offset o arrives from: x - o
 __device__ __forceinline__ int from3(const int (&w)[3], int o) { return o > 0 ? w[1] : (o < 0 ? w[2] : w[0]); }
 
-template <class L, int TX, int TY>
+template <class L, int TX, int TY, bool WALL>
 __global__ __launch_bounds__(TX * TY) void bin_step_kernel(BinArgs a)
 {
     constexpr int Q = L::Q, NT = TX * TY;
@@ -252,14 +260,29 @@ __global__ __launch_bounds__(TX * TY) void bin_step_kernel(BinArgs a)
         wrap3(y0 + ly, a.ny, ry[k]);
     }
 
+    // Address of the population of direction i arriving at (X[0], Y[0], P[0]).
+    // With walls, a direction whose source plane lies beyond a wall (the
+    // same for the whole workgroup) reads the own site's opposite direction:
+    // the choice is made on the 32-bit direction and coordinates, and one
+    // address is formed from them.
     auto src_index = [&](const int (&X)[3], const int (&Y)[3], const int (&P)[3], int i) {
+        if (WALL && op<L>(i) != 0) {
+            const bool b = op<L>(i) > 0 ? P[0] == 0 : P[0] == a.np - 1;
+            const int dir = b ? opp<L>(i) : i;
+            const int xs = b ? X[0] : from3(X, ox<L>(i));
+            const int ys = b ? Y[0] : from3(Y, oy<L>(i));
+            const int ps = b ? P[0] : from3(P, op<L>(i));
+            return (long long)dir * a.stride + (long long)ps * nxy + (long long)ys * a.nx + xs;
+        }
         return (long long)i * a.stride + (long long)from3(P, op<L>(i)) * nxy +
                (long long)from3(Y, oy<L>(i)) * a.nx + from3(X, ox<L>(i));
     };
     // phi of plane p for every ring entry, into ring slot s; the own site's
-    // arriving g into gown
+    // arriving g into gown.  With walls a plane beyond a wall is the mirror
+    // image of the one inside it.
     auto form_phi = [&](int p, int s, double (&gown)[Q]) {
         int P[3];
+        if (WALL) p = p < 0 ? -1 - p : (p >= a.np ? 2 * a.np - 1 - p : p);
         wrap3(p, a.np, P);
 #pragma unroll
         for (int k = 0; k < NIT; k++) {
@@ -313,10 +336,37 @@ __global__ __launch_bounds__(TX * TY) void bin_step_kernel(BinArgs a)
     }
 }
 
-// f = f^eq(rho0, rho0 u0, phi0), g = g^eq(phi0, u0) with the stencils applied
-// to phi0, stored in the pull layout (at r - e_i).
+// Pull-layout address of the population of direction i arriving at (x, y, p):
+// S[i][r - e_i], or S[opp(i)][r] when r - e_i lies beyond a wall.
 template <class L>
-__global__ void bin_init_kernel(Geom g, BinCoefs c, const double *__restrict__ rho0,
+__device__ __forceinline__ long long bin_arrival(const Geom &g, bool wall, int x, int y, int p, int i)
+{
+    if (wall && op<L>(i) != 0) {
+        const int ps = p - op<L>(i);
+        if (ps < 0 || ps >= g.np) return (long long)opp<L>(i) * g.stride + site_index<L>(g, x, y, p);
+    }
+    return (long long)i * g.stride + neighbour<L>(g, x, y, p, i, -1);
+}
+
+// Site r + e_i read by a stencil; a plane beyond a wall is mirrored.
+template <class L>
+__device__ __forceinline__ long long bin_stencil_site(const Geom &g, bool wall, int x, int y, int p, int i)
+{
+    if (wall && op<L>(i) != 0) {
+        const int pn = p + op<L>(i);
+        if (pn < 0 || pn >= g.np) {
+            const int xs = wrap1(x + ox<L>(i), g.nx);
+            const int ys = L::DIM == 3 ? wrap1(y + oy<L>(i), g.ny) : 0;
+            return site_index<L>(g, xs, ys, pn < 0 ? 0 : g.np - 1);
+        }
+    }
+    return neighbour<L>(g, x, y, p, i, +1);
+}
+
+// f = f^eq(rho0, rho0 u0, phi0), g = g^eq(phi0, u0) with the stencils applied
+// to phi0, stored in the pull layout (where each population is read).
+template <class L>
+__global__ void bin_init_kernel(Geom g, BinCoefs c, bool wall, const double *__restrict__ rho0,
                                 const double *__restrict__ phi0, const double *__restrict__ u0,
                                 double *__restrict__ fdst, double *__restrict__ gdst)
 {
@@ -328,7 +378,7 @@ __global__ void bin_init_kernel(Geom g, BinCoefs c, const double *__restrict__ r
     double d[3] = {0, 0, 0}, lap = 0;
 #pragma unroll
     for (int i = 1; i < L::Q; i++) {
-        const double v = phi0[neighbour<L>(g, x, y, p, i, +1)];
+        const double v = phi0[bin_stencil_site<L>(g, wall, x, y, p, i)];
         const double cg = bin_grad_coef<L>(c, i) * v;
         d[0] += L::ex[i] * cg;
         d[1] += L::ey[i] * cg;
@@ -363,19 +413,19 @@ __global__ void bin_init_kernel(Geom g, BinCoefs c, const double *__restrict__ r
         fin[2 + 2 * a] -= half;
     }
     const BinSite st = bin_collide_f<L>(ce, fin, phi, d, lap, [&](int i, double v) {
-        fdst[(long long)i * g.stride + neighbour<L>(g, x, y, p, i, -1)] = v;
+        fdst[bin_arrival<L>(g, wall, x, y, p, i)] = v;
     });
     bin_collide_g<L>(ce, gin, st, [&](int i, double v) {
-        gdst[(long long)i * g.stride + neighbour<L>(g, x, y, p, i, -1)] = v;
+        gdst[bin_arrival<L>(g, wall, x, y, p, i)] = v;
     });
 }
 
 // Observables of the pulled state: rho, phi, u = j / rho (for mu, a second
 // pass applies the Laplacian to phi).
 template <class L>
-__global__ void bin_moments_kernel(Geom g, const double *__restrict__ fsrc, const double *__restrict__ gsrc,
-                                   double *__restrict__ rho_out, double *__restrict__ phi_out,
-                                   double *__restrict__ vel_out)
+__global__ void bin_moments_kernel(Geom g, bool wall, const double *__restrict__ fsrc,
+                                   const double *__restrict__ gsrc, double *__restrict__ rho_out,
+                                   double *__restrict__ phi_out, double *__restrict__ vel_out)
 {
     const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= g.n) return;
@@ -384,7 +434,7 @@ __global__ void bin_moments_kernel(Geom g, const double *__restrict__ fsrc, cons
     double rho = 0, phi = 0, j[3] = {0, 0, 0};
 #pragma unroll
     for (int i = 0; i < L::Q; i++) {
-        const long long k = (long long)i * g.stride + neighbour<L>(g, x, y, p, i, -1);
+        const long long k = bin_arrival<L>(g, wall, x, y, p, i);
         const double v = fsrc[k];
         rho += v;
         phi += gsrc[k];
@@ -403,7 +453,8 @@ __global__ void bin_moments_kernel(Geom g, const double *__restrict__ fsrc, cons
 
 // mu = pa phi + pb phi^3 - kappa lap(phi) from a phi field
 template <class L>
-__global__ void bin_mu_kernel(Geom g, BinCoefs c, const double *__restrict__ phi, double *__restrict__ mu)
+__global__ void bin_mu_kernel(Geom g, BinCoefs c, bool wall, const double *__restrict__ phi,
+                              double *__restrict__ mu)
 {
     const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= g.n) return;
@@ -412,8 +463,26 @@ __global__ void bin_mu_kernel(Geom g, BinCoefs c, const double *__restrict__ phi
     const double v0 = phi[s];
     double lap = 0;
 #pragma unroll
-    for (int i = 1; i < L::Q; i++) lap += bin_lap_coef<L>(c, i) * (phi[neighbour<L>(g, x, y, p, i, +1)] - v0);
+    for (int i = 1; i < L::Q; i++) lap += bin_lap_coef<L>(c, i) * (phi[bin_stencil_site<L>(g, wall, x, y, p, i)] - v0);
     mu[s] = c.pa * v0 + c.pb * v0 * v0 * v0 - c.kappa * lap;
+}
+
+// Post-streaming populations out[i][r] (the populations arriving at r) from
+// the pull layout, or (set) the reverse.
+template <class L>
+__global__ void bin_state_kernel(Geom g, bool wall, bool get, const double *__restrict__ in,
+                                 double *__restrict__ out)
+{
+    const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= g.n) return;
+    int x, y, p;
+    site_coords<L>(g, s, x, y, p);
+#pragma unroll
+    for (int i = 0; i < L::Q; i++) {
+        const long long k = bin_arrival<L>(g, wall, x, y, p, i);
+        if (get) out[(long long)i * g.stride + s] = in[k];
+        else out[k] = in[(long long)i * g.stride + s];
+    }
 }
 
 } // namespace lbm

@@ -44,6 +44,7 @@ bool bin_valid(const lbm_bin_params *p)
     if (!(p->kappa >= 0.0) || !std::isfinite(p->kappa)) return false;
     if (!(p->gamma >= 0.0) || !std::isfinite(p->gamma)) return false;
     if (p->tile >= bin_tile_count(p->lattice)) return false;
+    if (p->wall != 0 && p->wall != 1) return false;
     if (p->lattice == LBM_D3Q19 &&
         (!std::isnan(p->wp_diag) || !std::isnan(p->wt_diag) || !std::isnan(p->wxx_diag)))
         return false;
@@ -127,7 +128,10 @@ int bin_default_planes(const lbm_bin_ctx *c, int tile)
 
 template <class L, int TX, int TY> void bin_launch_t(lbm_bin_ctx *c, const BinArgs &a, int nblk)
 {
-    bin_step_kernel<L, TX, TY><<<nblk, TX * TY, 0, c->stream>>>(a);
+    if (c->p.wall)
+        bin_step_kernel<L, TX, TY, true><<<nblk, TX * TY, 0, c->stream>>>(a);
+    else
+        bin_step_kernel<L, TX, TY, false><<<nblk, TX * TY, 0, c->stream>>>(a);
 }
 
 void bin_launch_step(lbm_bin_ctx *c)
@@ -160,10 +164,10 @@ void bin_launch_step(lbm_bin_ctx *c)
 void bin_launch_moments(lbm_bin_ctx *c, double *rho, double *phi, double *vel)
 {
     if (c->p.lattice == LBM_D2Q9)
-        bin_moments_kernel<D2Q9><<<grid1(c->n), 256, 0, c->stream>>>(bin_geom(c), bin_f(c, c->cur),
+        bin_moments_kernel<D2Q9><<<grid1(c->n), 256, 0, c->stream>>>(bin_geom(c), c->p.wall, bin_f(c, c->cur),
                                                                       bin_g(c, c->cur), rho, phi, vel);
     else
-        bin_moments_kernel<D3Q19><<<grid1(c->n), 256, 0, c->stream>>>(bin_geom(c), bin_f(c, c->cur),
+        bin_moments_kernel<D3Q19><<<grid1(c->n), 256, 0, c->stream>>>(bin_geom(c), c->p.wall, bin_f(c, c->cur),
                                                                        bin_g(c, c->cur), rho, phi, vel);
 }
 
@@ -196,8 +200,18 @@ template <class L> int bin_pop_sums(lbm_bin_ctx *c, const double *src, double *h
 template <class L> int bin_totals_t(lbm_bin_ctx *c, double *mass, double *phi_total, double *mom)
 {
     double hf[19], hg[19];
-    int rc = bin_pop_sums<L>(c, bin_f(c, c->cur), hf);
-    if (rc == LBM_OK) rc = bin_pop_sums<L>(c, bin_g(c, c->cur), hg);
+    // Every stored entry is read once per step, so its per-direction sums
+    // give the totals; with walls a bounced entry arrives reversed, so the
+    // state is first streamed into the idle buffers (free between steps).
+    const double *fs = bin_f(c, c->cur), *gs = bin_g(c, c->cur);
+    if (c->p.wall) {
+        bin_state_kernel<L><<<grid1(c->n), 256, 0, c->stream>>>(bin_geom(c), true, true, fs, bin_f(c, c->cur ^ 1));
+        bin_state_kernel<L><<<grid1(c->n), 256, 0, c->stream>>>(bin_geom(c), true, true, gs, bin_g(c, c->cur ^ 1));
+        fs = bin_f(c, c->cur ^ 1);
+        gs = bin_g(c, c->cur ^ 1);
+    }
+    int rc = bin_pop_sums<L>(c, fs, hf);
+    if (rc == LBM_OK) rc = bin_pop_sums<L>(c, gs, hg);
     if (rc != LBM_OK) return rc;
     double m = 0, ph = 0, mx = 0, my = 0, mz = 0;
     for (int i = 0; i < L::Q; i++) {
@@ -219,13 +233,13 @@ template <class L> int bin_totals_t(lbm_bin_ctx *c, double *mass, double *phi_to
 
 template <class L> void bin_state_io_t(lbm_bin_ctx *c, double *fo, double *go, const double *fi, const double *gi)
 {
-    const Coefs<double> z{};  // no storage shift
+    const bool w = c->p.wall != 0;
     if (fo) {
-        get_state_kernel<L, double><<<grid1(c->n), 256, 0, c->stream>>>(bin_geom(c), z, bin_f(c, c->cur), fo);
-        get_state_kernel<L, double><<<grid1(c->n), 256, 0, c->stream>>>(bin_geom(c), z, bin_g(c, c->cur), go);
+        bin_state_kernel<L><<<grid1(c->n), 256, 0, c->stream>>>(bin_geom(c), w, true, bin_f(c, c->cur), fo);
+        bin_state_kernel<L><<<grid1(c->n), 256, 0, c->stream>>>(bin_geom(c), w, true, bin_g(c, c->cur), go);
     } else {
-        set_state_kernel<L, double><<<grid1(c->n), 256, 0, c->stream>>>(bin_geom(c), z, fi, bin_f(c, c->cur));
-        set_state_kernel<L, double><<<grid1(c->n), 256, 0, c->stream>>>(bin_geom(c), z, gi, bin_g(c, c->cur));
+        bin_state_kernel<L><<<grid1(c->n), 256, 0, c->stream>>>(bin_geom(c), w, false, fi, bin_f(c, c->cur));
+        bin_state_kernel<L><<<grid1(c->n), 256, 0, c->stream>>>(bin_geom(c), w, false, gi, bin_g(c, c->cur));
     }
 }
 
@@ -246,6 +260,7 @@ void lbm_bin_params_default(lbm_bin_params *p)
     p->nx = 100;
     p->ny = 100;
     p->nz = 1;
+    p->wall = 0;
     p->B = p->D = NAN;
     p->wp_diag = p->wt_diag = p->wxx_diag = NAN;
     p->tile = -1;
@@ -303,11 +318,11 @@ int lbm_bin_init(lbm_bin_ctx **out, const lbm_bin_params *p, void *dev_workspace
         return LBM_E_INVAL;
     }
     if (p->lattice == LBM_D2Q9)
-        bin_init_kernel<D2Q9><<<grid1(c->n), 256, 0, c->stream>>>(bin_geom(c), c->c, dev_rho0, dev_phi0, dev_u0,
-                                                                 bin_f(c, 0), bin_g(c, 0));
+        bin_init_kernel<D2Q9><<<grid1(c->n), 256, 0, c->stream>>>(bin_geom(c), c->c, p->wall, dev_rho0, dev_phi0,
+                                                                 dev_u0, bin_f(c, 0), bin_g(c, 0));
     else
-        bin_init_kernel<D3Q19><<<grid1(c->n), 256, 0, c->stream>>>(bin_geom(c), c->c, dev_rho0, dev_phi0, dev_u0,
-                                                                  bin_f(c, 0), bin_g(c, 0));
+        bin_init_kernel<D3Q19><<<grid1(c->n), 256, 0, c->stream>>>(bin_geom(c), c->c, p->wall, dev_rho0, dev_phi0,
+                                                                  dev_u0, bin_f(c, 0), bin_g(c, 0));
     if (hipGetLastError() != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess) {
         delete c;
         return LBM_E_DEVICE;
@@ -334,9 +349,9 @@ int lbm_bin_moments(lbm_bin_ctx *c, double *dev_rho, double *dev_phi, double *de
     bin_launch_moments(c, dev_rho, ph, dev_vel);
     if (dev_mu) {
         if (c->p.lattice == LBM_D2Q9)
-            bin_mu_kernel<D2Q9><<<grid1(c->n), 256, 0, c->stream>>>(bin_geom(c), c->c, ph, dev_mu);
+            bin_mu_kernel<D2Q9><<<grid1(c->n), 256, 0, c->stream>>>(bin_geom(c), c->c, c->p.wall, ph, dev_mu);
         else
-            bin_mu_kernel<D3Q19><<<grid1(c->n), 256, 0, c->stream>>>(bin_geom(c), c->c, ph, dev_mu);
+            bin_mu_kernel<D3Q19><<<grid1(c->n), 256, 0, c->stream>>>(bin_geom(c), c->c, c->p.wall, ph, dev_mu);
     }
     return hipGetLastError() == hipSuccess ? LBM_OK : LBM_E_DEVICE;
 }

@@ -75,6 +75,11 @@ CASES = [
     # stencil and weight overrides (the Fig. 2 parameters carried over)
     (9, (40, 31), 60, dict(B=0.0, wxx_diag=0.0)), (9, (33, 27), 60, dict(wp_diag=0.05, wt_diag=0.1, D=0.2)),
     (19, (20, 13, 9), 30, dict(B=0.0, D=0.2)),
+    # walls at both ends of the marching axis (halfway bounce-back, mirrored
+    # stencils): several planes, two planes, one plane between the walls
+    (9, (37, 29), 60, dict(wall=1)), (9, (33, 2), 30, dict(wall=1, tau=0.8)),
+    (19, (24, 20, 18), 40, dict(wall=1)), (19, (37, 11, 9), 30, dict(wall=1, tau=0.7, tau_phi=1.2)),
+    (19, (13, 9, 2), 20, dict(wall=1)), (19, (16, 12, 1), 20, dict(wall=1)),
 ]
 
 
@@ -108,10 +113,11 @@ def test_binary_matches_oracle(q, shape, nsteps, kw):
     sim.close()
 
 
-@pytest.mark.parametrize("q,shape", [(9, (200, 37)), (19, (70, 21, 13))])
-def test_binary_launch_shapes_agree_bitwise(q, shape):
+@pytest.mark.parametrize("q,shape,wall", [(9, (200, 37), 0), (19, (70, 21, 13), 0), (9, (130, 21), 1),
+                                          (19, (70, 21, 13), 1)])
+def test_binary_launch_shapes_agree_bitwise(q, shape, wall):
     lbm = _lbm()
-    gp, _ = _pair(q, shape, tau=0.9, tau_phi=1.2)
+    gp, _ = _pair(q, shape, tau=0.9, tau_phi=1.2, wall=wall)
     rho, phi, u = _fields(shape)
     ref = None
     for tile in range(lbm.lbm_bin_tile_count(q)):
@@ -149,7 +155,7 @@ def test_binary_rejects_bad_input():
     lbm = _lbm()
     gp, _ = _pair(9, (16, 16))
     for bad in (dict(tau=0.5), dict(tau_phi=0.4), dict(phi_b=-1.0), dict(kappa=-0.1),
-                dict(gamma=float("nan")), dict(tile=5), dict(nz=2)):
+                dict(gamma=float("nan")), dict(tile=5), dict(wall=2), dict(nz=2)):
         p = lbm.bin_params(lattice=9, shape=(16, 16), **bad) if "nz" not in bad else \
             lbm.bin_params(lattice=9, shape=(16, 16, 2))
         assert lbm.lbm_bin_workspace_bytes(p) == 0, bad
