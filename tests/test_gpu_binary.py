@@ -288,3 +288,33 @@ def test_full_size_binary_long_run_invariants():
     assert np.abs(np.subtract(j1, j0)).max() < 1e-14 * n
     assert np.isfinite(umax) and umax < 1e-2
     sim.close()
+
+
+@pytest.mark.parametrize("q,shape", [(9, (16, 64)), (19, (16, 8, 64))])
+def test_walls_shear_mode_and_conservation_on_the_gpu(q, shape):
+    """Walls at both ends of the marching axis: the no-slip shear mode
+    u_x = U sin(pi (z + 1/2) / n) decays at nu (pi / n)^2 (halfway
+    bounce-back walls at -1/2 and n - 1/2), while mass and the order
+    parameter stay constant to round-off."""
+    lbm = _lbm()
+    nz, tau = shape[-1], 0.8
+    rows = int(np.prod(shape)) // nz
+    gp, _ = _pair(q, shape, tau=tau, wall=1)
+    prof = np.sin(np.pi * (np.arange(nz) + 0.5) / nz)
+    u0 = np.zeros((3, rows * nz))
+    u0[0] = np.repeat(1e-3 * prof, rows)
+    sim = lbm.BinarySimulation(gp, np.ones(rows * nz), np.ones(rows * nz), u0)
+    m0, p0, _ = sim.invariants()
+    amps = []
+    for steps in (500, 3000):
+        sim.step(steps)
+        v = sim.moments()[2][0].cpu().numpy().reshape(nz, rows)[:, 0]
+        amps.append(2 * np.mean(v * prof))
+    m1, p1, _ = sim.invariants()
+    rate = np.log(amps[0] / amps[1]) / 3000
+    want = (tau - 0.5) / 3 * (np.pi / nz) ** 2
+    _say("walls q", q, "shear decay rate", rate, "theory", want)
+    assert abs(rate / want - 1) < 2e-3
+    n = rows * nz
+    assert abs(m1 - m0) < 1e-13 * n and abs(p1 - p0) < 1e-13 * n
+    sim.close()
