@@ -210,11 +210,12 @@ class OrcBinParams(ctypes.Structure):
 
 
 def bin_params(q=9, shape=(64, 64), phi_a=-0.02, phi_b=0.02, kappa=0.04, tau=1.0,
-               tau_phi=1.0, gamma=1.0, wall=0, **over):
+               tau_phi=1.0, gamma=1.0, wall=0, scheme=0, **over):
     """Symmetric binary fluid: bulk free energy phi_a phi^2/2 + phi_b phi^4/4
     plus kappa |grad phi|^2 / 2, ideal-gas carrier rho/3.  wall = 1 bounds
-    the last axis (z in 3D, y in 2D) by two halfway bounce-back walls."""
-    base = params(q=q, scheme=0, shape=shape, a=0.0, b=0.0, T=0.0, kappa=kappa, tau=tau,
+    the last axis (z in 3D, y in 2D) by two halfway bounce-back walls;
+    scheme = 1 is the forcing scheme (periodic only)."""
+    base = params(q=q, scheme=scheme, shape=shape, a=0.0, b=0.0, T=0.0, kappa=kappa, tau=tau,
                   lambda_on=0, **over)
     return OrcBinParams(base, phi_a, phi_b, gamma, tau_phi, int(wall))
 

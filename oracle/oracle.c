@@ -723,7 +723,13 @@ int orc_max_threads(void)
  *     w_i, and g_0 closes the zeroth moment;
  *   - gradients and Laplacians with the same stencils as the liquid-gas
  *     model (Eqs. (xderiv), (laplace), (laplacian3d)).
- * Only the tuned-equilibrium scheme is defined for the binary fluid.
+ * The forcing scheme (base.scheme = 1) carries over the same way: the f
+ * equilibrium drops the w^ab terms, and the body force g_a = -d_b (M_ab -
+ * delta_ab M_gg / 2), M_ab = kappa d_a phi d_b phi, with the force stencil,
+ * enters f through the forcing terms of section "Using a forcing method"
+ * (F_i with u = j / rho, F_0 = -sum F_i); the order parameter is advected by
+ * the fluid velocity of that scheme, v = u + g / (2 rho), which is also the
+ * reported velocity.  Walls are not combined with the forcing scheme.
  */
 typedef struct {
     orc_params base;     /* q, extent, kappa, tau, stencils, weights */
@@ -825,6 +831,7 @@ static void feq_bin_site_t(const orc_bin_params *bp, const tables *t, double rho
     double M[6] = {kappa * grad[0] * grad[0], kappa * grad[1] * grad[1],
                    kappa * grad[2] * grad[2], kappa * grad[0] * grad[1],
                    kappa * grad[1] * grad[2], kappa * grad[2] * grad[0]};
+    const int with_m = bp->base.scheme == 0; /* the forcing scheme moves M into the force */
     double sum = 0.0;
     for (int i = 1; i < t->q; i++) {
         const int *e = t->e[i];
@@ -834,7 +841,8 @@ static void feq_bin_site_t(const orc_bin_params *bp, const tables *t, double rho
             for (int be = 0; be < dim; be++)
                 ex += (e[al] * e[be] - (al == be ? 1.0 / 3.0 : 0.0)) * rho * u[al] * u[be];
         double v = t->w[i] * (ej + 1.5 * ex) + t->wp[i] * p0 - t->wt[i] * kappa * phi * lap;
-        for (int m = 0; m < 6; m++) v += t->wm[m][i] * M[m];
+        if (with_m)
+            for (int m = 0; m < 6; m++) v += t->wm[m][i] * M[m];
         feq[i] = v;
         sum += v;
     }
@@ -866,6 +874,8 @@ static int bin_valid(const orc_bin_params *bp)
     const orc_params *p = &bp->base;
     if (!(p->q == 9 || p->q == 19)) return 0;
     if (p->q == 9 && p->nz != 1) return 0;
+    if (p->scheme != 0 && p->scheme != 1) return 0;
+    if (p->scheme == 1 && bp->wall) return 0;
     return p->nx > 0 && p->ny > 0 && p->nz > 0;
 }
 
@@ -930,11 +940,14 @@ int orc_bin_run(const orc_bin_params *bp, double *f, double *g, int nsteps)
     double *phi = (double *)malloc(sizeof(double) * n);
     double *grad = (double *)malloc(sizeof(double) * 3 * n);
     double *lap = (double *)malloc(sizeof(double) * n);
+    const int force = p->scheme == 1;
+    double *gbody = (double *)malloc(sizeof(double) * 3 * n);
     double *fc = f, *gc = g, *fn = fb, *gn = gb;
     for (int step = 0; step < nsteps; step++) {
         moments(p, &t, fc, rho, j);
         order_parameter(p, &t, gc, phi);
         bin_derivatives(bp, &t, phi, grad, lap);
+        if (force) body_force(p, &t, grad, gbody); /* periodic: no walls here */
 #pragma omp parallel for collapse(2) schedule(static)
         for (int z = 0; z < p->nz; z++)
             for (int y = 0; y < p->ny; y++)
@@ -943,9 +956,15 @@ int orc_bin_run(const orc_bin_params *bp, double *f, double *g, int nsteps)
                     double jj[3] = {j[s], j[n + s], j[2 * n + s]};
                     double u[3] = {jj[0] / rho[s], jj[1] / rho[s], jj[2] / rho[s]};
                     double d[3] = {grad[s], grad[n + s], grad[2 * n + s]};
-                    double fe[19], ge[19];
+                    double fe[19], ge[19], F[19] = {0};
+                    double vg[3] = {u[0], u[1], u[2]}; /* advecting velocity of phi */
+                    if (force) {
+                        double gs[3] = {gbody[s], gbody[n + s], gbody[2 * n + s]};
+                        force_site_t(&t, u, gs, F);
+                        for (int a = 0; a < 3; a++) vg[a] += gs[a] / (2.0 * rho[s]);
+                    }
                     feq_bin_site_t(bp, &t, rho[s], jj, phi[s], d, lap[s], fe);
-                    geq_bin_site_t(bp, &t, phi[s], u, bin_mu(bp, phi[s], lap[s]), ge);
+                    geq_bin_site_t(bp, &t, phi[s], vg, bin_mu(bp, phi[s], lap[s]), ge);
                     for (int i = 0; i < q; i++) {
                         const int *e = t.e[i];
                         /* into a wall: back to this site, reversed */
@@ -953,7 +972,7 @@ int orc_bin_run(const orc_bin_params *bp, double *f, double *g, int nsteps)
                                        ? (long)opposite(&t, i) * n + s
                                        : i * n + sidx(p, x + e[0], y + e[1], z + e[2]);
                         double fi = fc[i * n + s], gi = gc[i * n + s];
-                        fn[dst] = fi - (fi - fe[i]) / p->tau;
+                        fn[dst] = fi - (fi - fe[i]) / p->tau + F[i];
                         gn[dst] = gi - (gi - ge[i]) / bp->tau_phi;
                     }
                 }
@@ -964,7 +983,7 @@ int orc_bin_run(const orc_bin_params *bp, double *f, double *g, int nsteps)
         memcpy(f, fc, sizeof(double) * n * q);
         memcpy(g, gc, sizeof(double) * n * q);
     }
-    free(fb); free(gb); free(rho); free(j); free(phi); free(grad); free(lap);
+    free(fb); free(gb); free(rho); free(j); free(phi); free(grad); free(lap); free(gbody);
     return 0;
 }
 
@@ -985,13 +1004,17 @@ int orc_bin_observe(const orc_bin_params *bp, const double *f, const double *g, 
     moments(p, &t, f, r, j);
     order_parameter(p, &t, g, ph);
     bin_derivatives(bp, &t, ph, grad, lap);
+    double *gbody = (double *)calloc(3 * n, sizeof(double));
+    if (p->scheme == 1) body_force(p, &t, grad, gbody);
     for (long s = 0; s < n; s++) {
         if (rho) rho[s] = r[s];
         if (phi) phi[s] = ph[s];
-        if (vel)
-            for (int a = 0; a < 3; a++) vel[a * n + s] = j[a * n + s] / r[s];
+        if (vel) /* u, plus g / (2 rho) for the forcing scheme */
+            for (int a = 0; a < 3; a++)
+                vel[a * n + s] = j[a * n + s] / r[s] + gbody[a * n + s] / (2.0 * r[s]);
         if (mu) mu[s] = bin_mu(bp, ph[s], lap[s]);
     }
+    free(gbody);
     free(r); free(j); free(ph); free(grad); free(lap);
     return 0;
 }
@@ -1067,12 +1090,36 @@ int orc_bin_collide_sites(const orc_bin_params *bp, const double *f, const doubl
                 }
         double phi = rho_at(p, &t, g, x, y, z);
         double u[3] = {j[0] / rho, j[1] / rho, j[2] / rho};
-        double fe[19], ge[19];
+        double fe[19], ge[19], F[19] = {0};
+        double vg[3] = {u[0], u[1], u[2]};
+        if (p->scheme == 1) {
+            /* g_a = -sum_b sum_stencil k * T_ab(neighbour), the phi gradient at
+             * each neighbour from the sums of g around it */
+            const double(*fs[3])[3][3] = {t.fx, t.fy, t.fz};
+            double gb[3] = {0, 0, 0};
+            for (int sl = 0; sl < 3; sl++)
+                for (int r = 0; r < 3; r++)
+                    for (int c = 0; c < 3; c++) {
+                        int any = 0;
+                        for (int be = 0; be < t.dim; be++) any |= (fs[be][sl][r][c] != 0.0);
+                        if (!any) continue;
+                        double dn[3];
+                        grad_at(p, &t, g, x + c - 1, y + 1 - r, z + 1 - sl, dn);
+                        double tr = 0.0;
+                        for (int g2 = 0; g2 < t.dim; g2++) tr += p->kappa * dn[g2] * dn[g2];
+                        for (int al = 0; al < t.dim; al++)
+                            for (int be = 0; be < t.dim; be++)
+                                gb[al] -= fs[be][sl][r][c] *
+                                          (p->kappa * dn[al] * dn[be] - (al == be ? 0.5 * tr : 0.0));
+                    }
+            force_site_t(&t, u, gb, F);
+            for (int a = 0; a < 3; a++) vg[a] += gb[a] / (2.0 * rho);
+        }
         feq_bin_site_t(bp, &t, rho, j, phi, d, lap, fe);
-        geq_bin_site_t(bp, &t, phi, u, bin_mu(bp, phi, lap), ge);
+        geq_bin_site_t(bp, &t, phi, vg, bin_mu(bp, phi, lap), ge);
         for (int i = 0; i < t.q; i++) {
             double fi = f[i * n + s], gi = g[i * n + s];
-            fout[(long)k * t.q + i] = fi - (fi - fe[i]) / p->tau;
+            fout[(long)k * t.q + i] = fi - (fi - fe[i]) / p->tau + F[i];
             gout[(long)k * t.q + i] = gi - (gi - ge[i]) / bp->tau_phi;
         }
     }
