@@ -44,9 +44,10 @@ WORKLOADS = {
 # binary fluid (FP64 f and g): name: (lattice, shape); phi_a = -0.02,
 # phi_b = 0.02, kappa = 0.04, gamma = 1, tau = tau_phi = 1; a drop of
 # phi = +1 (radius side/4, tanh width 2) in phi = -1, rho = 1 + noise 0.01
-BIN_WORKLOADS = {
-    "d3q19_256_fp64_binary": (19, (256, 256, 256)),
-    "d2q9_1024_fp64_binary": (9, (1024, 1024)),
+BIN_WORKLOADS = {  # name: (lattice, shape, scheme)
+    "d3q19_256_fp64_binary": (19, (256, 256, 256), 0),
+    "d2q9_1024_fp64_binary": (9, (1024, 1024), 0),
+    "d3q19_256_fp64_binary_force": (19, (256, 256, 256), 1),
 }
 BIN_PARAMS = dict(phi_a=-0.02, phi_b=0.02, kappa=0.04, gamma=1.0, tau=1.0, tau_phi=1.0)
 BIN_KERNEL_SOURCES = ["paper_0710_5470_amd/csrc/lbm_binary.h", "paper_0710_5470_amd/csrc/lbm_lattice.h",
@@ -184,10 +185,10 @@ def cpu_baseline(wl):
 def make_binary(wl):
     """lbm_bin_params and the initial (rho, phi) of a binary workload."""
     from paper_0710_5470_amd import inputs, lbm
-    q, shape = BIN_WORKLOADS[wl]
+    q, shape, scheme = BIN_WORKLOADS[wl]
     phi = inputs.tanh_drop(shape, shape[0] / 4.0, 1.0, -1.0, 2.0)
     rho = 1.0 + inputs.uniform_noise(shape, 0.01, 41)
-    return lbm.bin_params(lattice=q, shape=shape, **BIN_PARAMS), rho, phi
+    return lbm.bin_params(lattice=q, shape=shape, scheme=scheme, **BIN_PARAMS), rho, phi
 
 
 def cpu_baseline_binary(wl):
@@ -197,11 +198,11 @@ def cpu_baseline_binary(wl):
     import numpy as np
     import oracle
     from paper_0710_5470_amd import inputs
-    q, shape = BIN_WORKLOADS[wl]
+    q, shape, scheme = BIN_WORKLOADS[wl]
     sample = (256, 256, 24) if q == 19 else (1024, 1024)
     phi = inputs.tanh_drop(sample, min(sample) / 3.0, 1.0, -1.0, 2.0)
     rho = 1.0 + inputs.uniform_noise(sample, 0.01, 41)
-    bp = oracle.bin_params(q=q, shape=sample, **BIN_PARAMS)
+    bp = oracle.bin_params(q=q, shape=sample, scheme=scheme, **BIN_PARAMS)
     f, g = oracle.bin_init(bp, rho, phi)
     steps = 36 if q == 19 else 100
     cores = oracle.max_threads()
@@ -225,7 +226,7 @@ def bench_binary(args):
     import torch
     from paper_0710_5470_amd import autotune, lbm
     wl = args.workload
-    q, shape = BIN_WORKLOADS[wl]
+    q, shape, scheme = BIN_WORKLOADS[wl]
     p, rho, phi = make_binary(wl)
     sim = lbm.BinarySimulation(p, rho, phi)
     n = sim.n
@@ -270,7 +271,8 @@ def bench_binary(args):
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": wl, "lattice": "D3Q19" if q == 19 else "D2Q9", "extent": list(shape),
-                   "model": "binary fluid", **BIN_PARAMS,
+                   "model": "binary fluid", "scheme": "force" if scheme else "equilibrium",
+                   **BIN_PARAMS,
                    "init": "phi drop R=%g (tanh width 2) + rho noise 0.01 (seed 41)" % (shape[0] / 4.0),
                    "launch": {"tile": lbm.lbm_bin_tile_shape(q, tile), "planes_per_workgroup": planes,
                               "workgroups": wgs, "autotuned": tuned}},
@@ -278,7 +280,10 @@ def bench_binary(args):
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
                      "traffic": measured_traffic(wl), "bytes_per_site": bytes_site,
-                     "kernel_ms": round(kern_ms, 5)},
+                     "kernel_ms": round(kern_ms, 5),
+                     # the forcing scheme's step is four launches (phi, stress,
+                     # divergence, the fused march); kernel_ms covers all four
+                     "launches_per_step": 4 if scheme else 1},
         "state_after": {"finite": ok, "max_vel": vmax, "mass": mass, "phi_total": phi_total,
                         "momentum": mom},
     }

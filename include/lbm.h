@@ -409,6 +409,14 @@ typedef struct {
      * wall (zero normal derivative, a neutral wall).  The paper defines no
      * walls; the forcing section only notes they are harder with forcing. */
     int wall;
+    /* LBM_SCHEME_EQ (the tuned equilibrium above) or LBM_SCHEME_FORCE: the
+     * forcing scheme of section "Using a forcing method" carried over, i.e.
+     * an f equilibrium without the w^ab terms and a body force
+     * g = -div(kappa d phi d phi - delta kappa |d phi|^2 / 2) with the force
+     * stencil (F_i as in the liquid-gas API), phi advected by and the
+     * reported velocity equal to v = u + g / (2 rho).  Periodic only: the
+     * forcing scheme with wall = 1 is LBM_E_INVAL. */
+    int scheme;
     /* Stencil and weight overrides as in lbm_params (NaN = the paper's
      * optimum): B, D the gradient and Laplacian off-axis coefficients;
      * wp_diag, wt_diag, wxx_diag the D2Q9 weights w^p_5-8, w^t_5-8,
@@ -420,7 +428,8 @@ typedef struct {
 } lbm_bin_params;
 
 /* phi_a = -0.02, phi_b = 0.02, kappa = 0.04, gamma = 1, tau = tau_phi = 1,
- * D2Q9 100 x 100, periodic, every override NaN, default launch. */
+ * D2Q9 100 x 100, periodic, equilibrium scheme, every override NaN, default
+ * launch. */
 void lbm_bin_params_default(lbm_bin_params *p);
 
 /* Bytes of device workspace (four population buffers, observation fields,
@@ -440,8 +449,9 @@ int lbm_bin_init(lbm_bin_ctx **out, const lbm_bin_params *p, void *dev_workspace
  * per step).  Only enqueues work. */
 int lbm_bin_step(lbm_bin_ctx *ctx, long long nsteps);
 
-/* rho [n], phi [n], u = j / rho [3][n] and mu [n] of the current state; any
- * pointer may be NULL.  Only enqueues work. */
+/* rho [n], phi [n], the velocity [3][n] (u = j / rho; v = u + g / (2 rho)
+ * for the forcing scheme) and mu [n] of the current state; any pointer may
+ * be NULL.  Only enqueues work. */
 int lbm_bin_moments(lbm_bin_ctx *ctx, double *dev_rho, double *dev_phi, double *dev_vel,
                     double *dev_mu);
 

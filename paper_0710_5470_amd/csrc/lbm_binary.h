@@ -57,6 +57,7 @@ struct BinCoefs {
     double omega, omega_g;       // 1 / tau, 1 / tau_phi
     double pa, pb;               // bulk free energy pa phi^2/2 + pb phi^4/4
     double gamma;                // mobility coefficient of the mu term
+    double Ef, Ff;               // force stencil: on-axis, off-axis
 };
 
 struct BinArgs {
@@ -68,6 +69,7 @@ struct BinArgs {
     int nx, ny, np;              // in-plane x, in-plane y (1 for D2Q9), planes
     long long stride;            // elements between direction arrays
     int tiles_x, tiles_y, cp;    // tiles per in-plane axis, planes per workgroup
+    const double *__restrict__ force;  // forcing scheme: body force [3][n]
 };
 
 template <class L> __device__ __forceinline__ double bin_grad_coef(const BinCoefs &c, int i)
@@ -106,10 +108,15 @@ struct BinSite {
 // order parameter there (the sum of the arriving g, formed by the caller in
 // the same order as the stencil's field); d, lap: gradient and Laplacian of
 // phi.  emit(i, v) receives each collided value.  Returns what the g
-// collision needs.
-template <class L, class EF>
+// collision needs.  FORCE (the forcing scheme): no w^ab terms in the
+// equilibrium; the body force gf enters through F_i = w_i (e.g + (3/2)
+// (e e - delta/3) : (u g + g u)), F_0 = -sum F_i, per pair of opposite
+// velocities fe = w (3 (e.u)(e.g) - u.g) and fd = w e.g; the returned
+// velocity (which advects phi) is v = u + g / (2 rho).
+template <class L, bool FORCE = false, class EF>
 __device__ __forceinline__ BinSite bin_collide_f(const BinCoefs &c, const double fin[L::Q], double phi,
-                                                 const double d[3], double lap, EF &&emit)
+                                                 const double d[3], double lap, EF &&emit,
+                                                 const double *gf = nullptr)
 {
     constexpr int Q = L::Q, DIM = L::DIM;
     BinSite s;
@@ -139,7 +146,9 @@ __device__ __forceinline__ BinSite bin_collide_f(const BinCoefs &c, const double
     const double stc[2] = {c.wp_ax * p0 - 1.5 * c.w_ax * trX3 - c.wt_ax * klap,
                            c.wp_off * p0 - 1.5 * c.w_off * trX3 - c.wt_off * klap};
     const double om = c.omega, keep = 1.0 - om;
-    double sumE = 0.0;
+    double ug = 0.0;
+    if (FORCE) ug = s.u[0] * gf[0] + s.u[1] * gf[1] + (DIM == 3 ? s.u[2] * gf[2] : 0.0);
+    double sumE = 0.0, sumF = 0.0;
 #pragma unroll
     for (int i = 1; i < Q; i++) {
         if (opp<L>(i) < i) continue;
@@ -148,13 +157,28 @@ __device__ __forceinline__ BinSite bin_collide_f(const BinCoefs &c, const double
         const double w = axis ? c.w_ax : c.w_off;
         const double eu = edot<L>(i, s.u);
         // even = (3/2) w rho (e.u)^2 + class terms + w^ab terms; odd = w e.j
-        const double even = 1.5 * w * rho * eu * eu + stc[axis ? 0 : 1] + bin_m_terms<L>(c, M, i);
+        double even = 1.5 * w * rho * eu * eu + stc[axis ? 0 : 1];
+        if (!FORCE) even += bin_m_terms<L>(c, M, i);
         const double odd = w * edot<L>(i, j);
         sumE += even;
-        emit(i, keep * fin[i] + om * (even + odd));
-        emit(o, keep * fin[o] + om * (even - odd));
+        double fe = 0.0, fd = 0.0;
+        if (FORCE) {
+            const double eg = edot<L>(i, gf);
+            fe = w * (3.0 * eu * eg - ug);
+            fd = w * eg;
+            sumF += fe;
+        }
+        emit(i, keep * fin[i] + om * (even + odd) + (fe + fd));
+        emit(o, keep * fin[o] + om * (even - odd) + (fe - fd));
     }
-    emit(0, keep * fin[0] + om * (rho - 2.0 * sumE));
+    emit(0, keep * fin[0] + om * (rho - 2.0 * sumE) - 2.0 * sumF);
+    if (FORCE) {
+        const double h = 0.5 * inv;
+        s.u[0] += gf[0] * h;
+        s.u[1] += gf[1] * h;
+        if (DIM == 3) s.u[2] += gf[2] * h;
+        s.uu = s.u[0] * s.u[0] + s.u[1] * s.u[1] + s.u[2] * s.u[2];
+    }
     return s;
 }
 
@@ -198,7 +222,7 @@ __device__ __forceinline__ void wrap3(int v, int n, int (&w)[3])
 // the coordinate a population of offset o arrives from: x - o
 __device__ __forceinline__ int from3(const int (&w)[3], int o) { return o > 0 ? w[1] : (o < 0 ? w[2] : w[0]); }
 
-template <class L, int TX, int TY, bool WALL>
+template <class L, int TX, int TY, bool WALL, bool FORCE = false>
 __global__ __launch_bounds__(TX * TY) void bin_step_kernel(BinArgs a)
 {
     constexpr int Q = L::Q, NT = TX * TY;
@@ -324,9 +348,15 @@ __global__ __launch_bounds__(TX * TY) void bin_step_kernel(BinArgs a)
             double fin[Q];
 #pragma unroll
             for (int i = 0; i < Q; i++) fin[i] = a.fsrc[src_index(rx[0], ry[0], P, i)];
-            const BinSite st = bin_collide_f<L>(a.c, fin, phi, d, lap, [&](int i, double v) {
+            double gf[3] = {0.0, 0.0, 0.0};
+            if (FORCE) {
+                gf[0] = a.force[site];
+                gf[1] = a.force[a.stride + site];
+                if (L::DIM == 3) gf[2] = a.force[2 * a.stride + site];
+            }
+            const BinSite st = bin_collide_f<L, FORCE>(a.c, fin, phi, d, lap, [&](int i, double v) {
                 __builtin_nontemporal_store(v, a.fdst + (long long)i * a.stride + site);
-            });
+            }, gf);
             bin_collide_g<L>(a.c, gcur, st, [&](int i, double v) {
                 __builtin_nontemporal_store(v, a.gdst + (long long)i * a.stride + site);
             });
@@ -365,7 +395,7 @@ __device__ __forceinline__ long long bin_stencil_site(const Geom &g, bool wall, 
 
 // f = f^eq(rho0, rho0 u0, phi0), g = g^eq(phi0, u0) with the stencils applied
 // to phi0, stored in the pull layout (where each population is read).
-template <class L>
+template <class L, bool FORCE>
 __global__ void bin_init_kernel(Geom g, BinCoefs c, bool wall, const double *__restrict__ rho0,
                                 const double *__restrict__ phi0, const double *__restrict__ u0,
                                 double *__restrict__ fdst, double *__restrict__ gdst)
@@ -412,9 +442,11 @@ __global__ void bin_init_kernel(Geom g, BinCoefs c, bool wall, const double *__r
         fin[1 + 2 * a] += half;
         fin[2 + 2 * a] -= half;
     }
-    const BinSite st = bin_collide_f<L>(ce, fin, phi, d, lap, [&](int i, double v) {
+    // (the forcing scheme's equilibrium: no w^ab terms, no force at rest)
+    const double zero[3] = {0.0, 0.0, 0.0};
+    const BinSite st = bin_collide_f<L, FORCE>(ce, fin, phi, d, lap, [&](int i, double v) {
         fdst[bin_arrival<L>(g, wall, x, y, p, i)] = v;
-    });
+    }, zero);
     bin_collide_g<L>(ce, gin, st, [&](int i, double v) {
         gdst[bin_arrival<L>(g, wall, x, y, p, i)] = v;
     });
@@ -424,8 +456,9 @@ __global__ void bin_init_kernel(Geom g, BinCoefs c, bool wall, const double *__r
 // pass applies the Laplacian to phi).
 template <class L>
 __global__ void bin_moments_kernel(Geom g, bool wall, const double *__restrict__ fsrc,
-                                   const double *__restrict__ gsrc, double *__restrict__ rho_out,
-                                   double *__restrict__ phi_out, double *__restrict__ vel_out)
+                                   const double *__restrict__ gsrc, const double *__restrict__ force,
+                                   double *__restrict__ rho_out, double *__restrict__ phi_out,
+                                   double *__restrict__ vel_out)
 {
     const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= g.n) return;
@@ -444,11 +477,87 @@ __global__ void bin_moments_kernel(Geom g, bool wall, const double *__restrict__
     }
     if (rho_out) rho_out[s] = rho;
     if (phi_out) phi_out[s] = phi;
-    if (vel_out) {
-        vel_out[s] = j[0] / rho;
-        vel_out[g.stride + s] = j[1] / rho;
-        vel_out[2 * g.stride + s] = L::DIM == 3 ? j[2] / rho : 0.0;
+    if (vel_out) {  // u, plus g / (2 rho) for the forcing scheme
+        double v[3] = {j[0] / rho, j[1] / rho, L::DIM == 3 ? j[2] / rho : 0.0};
+        if (force)
+            for (int a = 0; a < L::DIM; a++) v[a] += force[a * g.stride + s] / (2.0 * rho);
+        vel_out[s] = v[0];
+        vel_out[g.stride + s] = v[1];
+        vel_out[2 * g.stride + s] = v[2];
     }
+}
+
+// Forcing scheme, before each step: the order parameter phi = sum_i g_i of
+// the arriving populations (periodic lattices) ...
+template <class L>
+__global__ void bin_phi_kernel(Geom g, const double *__restrict__ gsrc, double *__restrict__ phi)
+{
+    const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= g.n) return;
+    int x, y, p;
+    site_coords<L>(g, s, x, y, p);
+    double v = 0.0;
+#pragma unroll
+    for (int i = 0; i < L::Q; i++) v += gsrc[(long long)i * g.stride + neighbour<L>(g, x, y, p, i, -1)];
+    phi[s] = v;
+}
+
+// ... the stress T_ab = kappa d_a phi d_b phi - delta_ab kappa |d phi|^2 / 2
+// with the gradient stencil, T[6][n] (xx, yy, zz, xy, yz, zx) ...
+template <class L>
+__global__ void bin_stress_kernel(Geom g, BinCoefs c, const double *__restrict__ phi, double *__restrict__ T)
+{
+    const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= g.n) return;
+    int x, y, p;
+    site_coords<L>(g, s, x, y, p);
+    double d[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int i = 1; i < L::Q; i++) {
+        const double v = bin_grad_coef<L>(c, i) * phi[neighbour<L>(g, x, y, p, i, +1)];
+        if (L::ex[i]) d[0] += L::ex[i] * v;
+        if (L::ey[i]) d[1] += L::ey[i] * v;
+        if (L::ez[i]) d[2] += L::ez[i] * v;
+    }
+    const double h = 0.5 * c.kappa * (d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    T[s] = c.kappa * d[0] * d[0] - h;
+    T[g.stride + s] = c.kappa * d[1] * d[1] - h;
+    T[2 * g.stride + s] = c.kappa * d[2] * d[2] - h;
+    T[3 * g.stride + s] = c.kappa * d[0] * d[1];
+    T[4 * g.stride + s] = c.kappa * d[1] * d[2];
+    T[5 * g.stride + s] = c.kappa * d[2] * d[0];
+}
+
+// ... and the body force g_a = -sum_b d_b T_ab with the force stencil
+// (section "Using a forcing method"), force[3][n].
+template <class L>
+__global__ void bin_divergence_kernel(Geom g, BinCoefs c, const double *__restrict__ T,
+                                      double *__restrict__ force)
+{
+    const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= g.n) return;
+    int x, y, p;
+    site_coords<L>(g, s, x, y, p);
+    // component (a, b) of T at row a: xx xy zx / xy yy yz / zx yz zz
+    constexpr int comp[3][3] = {{0, 3, 5}, {3, 1, 4}, {5, 4, 2}};
+    double f[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int i = 1; i < L::Q; i++) {
+        const long long nb = neighbour<L>(g, x, y, p, i, +1);
+        const double k = nnz<L>(i) == 1 ? c.Ef : c.Ff;
+#pragma unroll
+        for (int a = 0; a < L::DIM; a++) {
+#pragma unroll
+            for (int b = 0; b < L::DIM; b++) {
+                const int e = ecomp<L>(i, b);
+                if (e == 0) continue;
+                f[a] -= (k * e) * T[comp[a][b] * g.stride + nb];
+            }
+        }
+    }
+    force[s] = f[0];
+    force[g.stride + s] = f[1];
+    force[2 * g.stride + s] = L::DIM == 3 ? f[2] : 0.0;
 }
 
 // mu = pa phi + pb phi^3 - kappa lap(phi) from a phi field

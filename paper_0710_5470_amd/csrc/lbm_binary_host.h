@@ -11,7 +11,7 @@ struct lbm_bin_ctx {
     lbm_bin_params p;
     hipStream_t stream;
     char *ws;
-    size_t o_fa, o_fb, o_ga, o_gb, o_rho, o_phi, o_vel, o_part, o_res, total;
+    size_t o_fa, o_fb, o_ga, o_gb, o_rho, o_phi, o_vel, o_T, o_force, o_part, o_res, total;
     int cur;            // 0: state in (fa, ga), 1: in (fb, gb)
     long long steps;
     int tile, cp;
@@ -45,6 +45,8 @@ bool bin_valid(const lbm_bin_params *p)
     if (!(p->gamma >= 0.0) || !std::isfinite(p->gamma)) return false;
     if (p->tile >= bin_tile_count(p->lattice)) return false;
     if (p->wall != 0 && p->wall != 1) return false;
+    if (p->scheme != LBM_SCHEME_EQ && p->scheme != LBM_SCHEME_FORCE) return false;
+    if (p->scheme == LBM_SCHEME_FORCE && p->wall) return false;  // forcing: periodic only
     if (p->lattice == LBM_D3Q19 &&
         (!std::isnan(p->wp_diag) || !std::isnan(p->wt_diag) || !std::isnan(p->wxx_diag)))
         return false;
@@ -65,6 +67,9 @@ void bin_layout(lbm_bin_ctx *c)
     c->o_rho = o; o += align_up(n * 8);
     c->o_phi = o; o += align_up(n * 8);
     c->o_vel = o; o += align_up(3 * n * 8);
+    const size_t nf = c->p.scheme == LBM_SCHEME_FORCE ? n : 0;  // forcing scheme only
+    c->o_T = o; o += align_up(6 * nf * 8);
+    c->o_force = o; o += align_up(3 * nf * 8);
     c->o_part = o; o += align_up((size_t)RED_BLOCKS * 20 * 8);
     c->o_res = o; o += align_up(32 * 8);
     c->total = o;
@@ -101,6 +106,8 @@ BinCoefs bin_coefs(const lbm_bin_params *p)
     c.pa = p->phi_a;
     c.pb = p->phi_b;
     c.gamma = p->gamma;
+    c.Ef = k.Ef;
+    c.Ff = k.Ff;
     return c;
 }
 
@@ -128,10 +135,32 @@ int bin_default_planes(const lbm_bin_ctx *c, int tile)
 
 template <class L, int TX, int TY> void bin_launch_t(lbm_bin_ctx *c, const BinArgs &a, int nblk)
 {
-    if (c->p.wall)
+    if (c->p.scheme == LBM_SCHEME_FORCE)
+        bin_step_kernel<L, TX, TY, false, true><<<nblk, TX * TY, 0, c->stream>>>(a);
+    else if (c->p.wall)
         bin_step_kernel<L, TX, TY, true><<<nblk, TX * TY, 0, c->stream>>>(a);
     else
         bin_step_kernel<L, TX, TY, false><<<nblk, TX * TY, 0, c->stream>>>(a);
+}
+
+// Forcing scheme: the body force of the current state into the workspace
+// (phi field, stress, divergence); returns the force field, or nullptr for
+// the equilibrium scheme.
+const double *bin_body_force(lbm_bin_ctx *c)
+{
+    if (c->p.scheme != LBM_SCHEME_FORCE) return nullptr;
+    double *phi = bws(c, c->o_phi), *T = bws(c, c->o_T), *force = bws(c, c->o_force);
+    const Geom g = bin_geom(c);
+    if (c->p.lattice == LBM_D2Q9) {
+        bin_phi_kernel<D2Q9><<<grid1(c->n), 256, 0, c->stream>>>(g, bin_g(c, c->cur), phi);
+        bin_stress_kernel<D2Q9><<<grid1(c->n), 256, 0, c->stream>>>(g, c->c, phi, T);
+        bin_divergence_kernel<D2Q9><<<grid1(c->n), 256, 0, c->stream>>>(g, c->c, T, force);
+    } else {
+        bin_phi_kernel<D3Q19><<<grid1(c->n), 256, 0, c->stream>>>(g, bin_g(c, c->cur), phi);
+        bin_stress_kernel<D3Q19><<<grid1(c->n), 256, 0, c->stream>>>(g, c->c, phi, T);
+        bin_divergence_kernel<D3Q19><<<grid1(c->n), 256, 0, c->stream>>>(g, c->c, T, force);
+    }
+    return force;
 }
 
 void bin_launch_step(lbm_bin_ctx *c)
@@ -149,6 +178,7 @@ void bin_launch_step(lbm_bin_ctx *c)
     int chunks;
     bin_grid(c, c->tile, c->cp, a.tiles_x, a.tiles_y, chunks);
     a.cp = c->cp;
+    a.force = bin_body_force(c);
     const int nblk = a.tiles_x * a.tiles_y * chunks;
     if (c->p.lattice == LBM_D2Q9) {
         if (c->tile == 0) bin_launch_t<D2Q9, 128, 1>(c, a, nblk);
@@ -163,12 +193,13 @@ void bin_launch_step(lbm_bin_ctx *c)
 
 void bin_launch_moments(lbm_bin_ctx *c, double *rho, double *phi, double *vel)
 {
+    const double *force = vel ? bin_body_force(c) : nullptr;
     if (c->p.lattice == LBM_D2Q9)
-        bin_moments_kernel<D2Q9><<<grid1(c->n), 256, 0, c->stream>>>(bin_geom(c), c->p.wall, bin_f(c, c->cur),
-                                                                      bin_g(c, c->cur), rho, phi, vel);
+        bin_moments_kernel<D2Q9><<<grid1(c->n), 256, 0, c->stream>>>(
+            bin_geom(c), c->p.wall, bin_f(c, c->cur), bin_g(c, c->cur), force, rho, phi, vel);
     else
-        bin_moments_kernel<D3Q19><<<grid1(c->n), 256, 0, c->stream>>>(bin_geom(c), c->p.wall, bin_f(c, c->cur),
-                                                                       bin_g(c, c->cur), rho, phi, vel);
+        bin_moments_kernel<D3Q19><<<grid1(c->n), 256, 0, c->stream>>>(
+            bin_geom(c), c->p.wall, bin_f(c, c->cur), bin_g(c, c->cur), force, rho, phi, vel);
 }
 
 // reduce (rho, vel) into out[OBS_NV] (b = 0: a site is bad if non-finite or rho <= 0)
@@ -261,6 +292,7 @@ void lbm_bin_params_default(lbm_bin_params *p)
     p->ny = 100;
     p->nz = 1;
     p->wall = 0;
+    p->scheme = LBM_SCHEME_EQ;
     p->B = p->D = NAN;
     p->wp_diag = p->wt_diag = p->wxx_diag = NAN;
     p->tile = -1;
@@ -317,12 +349,17 @@ int lbm_bin_init(lbm_bin_ctx **out, const lbm_bin_params *p, void *dev_workspace
         delete c;
         return LBM_E_INVAL;
     }
-    if (p->lattice == LBM_D2Q9)
-        bin_init_kernel<D2Q9><<<grid1(c->n), 256, 0, c->stream>>>(bin_geom(c), c->c, p->wall, dev_rho0, dev_phi0,
-                                                                 dev_u0, bin_f(c, 0), bin_g(c, 0));
-    else
-        bin_init_kernel<D3Q19><<<grid1(c->n), 256, 0, c->stream>>>(bin_geom(c), c->c, p->wall, dev_rho0, dev_phi0,
-                                                                  dev_u0, bin_f(c, 0), bin_g(c, 0));
+    const bool force = p->scheme == LBM_SCHEME_FORCE;
+    const Geom g = bin_geom(c);
+    const unsigned nb = grid1(c->n);
+    double *f0 = bin_f(c, 0), *g0 = bin_g(c, 0);
+    if (p->lattice == LBM_D2Q9) {
+        if (force) bin_init_kernel<D2Q9, true><<<nb, 256, 0, c->stream>>>(g, c->c, p->wall, dev_rho0, dev_phi0, dev_u0, f0, g0);
+        else bin_init_kernel<D2Q9, false><<<nb, 256, 0, c->stream>>>(g, c->c, p->wall, dev_rho0, dev_phi0, dev_u0, f0, g0);
+    } else {
+        if (force) bin_init_kernel<D3Q19, true><<<nb, 256, 0, c->stream>>>(g, c->c, p->wall, dev_rho0, dev_phi0, dev_u0, f0, g0);
+        else bin_init_kernel<D3Q19, false><<<nb, 256, 0, c->stream>>>(g, c->c, p->wall, dev_rho0, dev_phi0, dev_u0, f0, g0);
+    }
     if (hipGetLastError() != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess) {
         delete c;
         return LBM_E_DEVICE;

@@ -123,7 +123,7 @@ class lbm_bin_params(ctypes.Structure):
         ("phi_a", ctypes.c_double), ("phi_b", ctypes.c_double), ("kappa", ctypes.c_double),
         ("gamma", ctypes.c_double), ("tau", ctypes.c_double), ("tau_phi", ctypes.c_double),
         ("lattice", ctypes.c_int), ("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
-        ("wall", ctypes.c_int),
+        ("wall", ctypes.c_int), ("scheme", ctypes.c_int),
         ("B", ctypes.c_double), ("D", ctypes.c_double),
         ("wp_diag", ctypes.c_double), ("wt_diag", ctypes.c_double), ("wxx_diag", ctypes.c_double),
         ("tile", ctypes.c_int), ("planes_per_block", ctypes.c_int),
