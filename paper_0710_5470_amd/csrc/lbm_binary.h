@@ -502,10 +502,10 @@ __global__ void bin_phi_kernel(Geom g, const double *__restrict__ gsrc, double *
     phi[s] = v;
 }
 
-// ... the stress T_ab = kappa d_a phi d_b phi - delta_ab kappa |d phi|^2 / 2
-// with the gradient stencil, T[6][n] (xx, yy, zz, xy, yz, zx) ...
+// ... the gradient d phi with the gradient stencil, dphi[3][n] ...
 template <class L>
-__global__ void bin_stress_kernel(Geom g, BinCoefs c, const double *__restrict__ phi, double *__restrict__ T)
+__global__ void bin_gradient_kernel(Geom g, BinCoefs c, const double *__restrict__ phi,
+                                    double *__restrict__ dphi)
 {
     const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= g.n) return;
@@ -519,39 +519,39 @@ __global__ void bin_stress_kernel(Geom g, BinCoefs c, const double *__restrict__
         if (L::ey[i]) d[1] += L::ey[i] * v;
         if (L::ez[i]) d[2] += L::ez[i] * v;
     }
-    const double h = 0.5 * c.kappa * (d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-    T[s] = c.kappa * d[0] * d[0] - h;
-    T[g.stride + s] = c.kappa * d[1] * d[1] - h;
-    T[2 * g.stride + s] = c.kappa * d[2] * d[2] - h;
-    T[3 * g.stride + s] = c.kappa * d[0] * d[1];
-    T[4 * g.stride + s] = c.kappa * d[1] * d[2];
-    T[5 * g.stride + s] = c.kappa * d[2] * d[0];
+    dphi[s] = d[0];
+    dphi[g.stride + s] = d[1];
+    if (L::DIM == 3) dphi[2 * g.stride + s] = d[2];
 }
 
 // ... and the body force g_a = -sum_b d_b T_ab with the force stencil
-// (section "Using a forcing method"), force[3][n].
+// (section "Using a forcing method"), T_ab = kappa d_a phi d_b phi -
+// delta_ab kappa |d phi|^2 / 2 formed at each neighbour from its gradient,
+// force[3][n].
 template <class L>
-__global__ void bin_divergence_kernel(Geom g, BinCoefs c, const double *__restrict__ T,
+__global__ void bin_divergence_kernel(Geom g, BinCoefs c, const double *__restrict__ dphi,
                                       double *__restrict__ force)
 {
     const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= g.n) return;
     int x, y, p;
     site_coords<L>(g, s, x, y, p);
-    // component (a, b) of T at row a: xx xy zx / xy yy yz / zx yz zz
-    constexpr int comp[3][3] = {{0, 3, 5}, {3, 1, 4}, {5, 4, 2}};
     double f[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int i = 1; i < L::Q; i++) {
         const long long nb = neighbour<L>(g, x, y, p, i, +1);
+        double d[3] = {dphi[nb], dphi[g.stride + nb], L::DIM == 3 ? dphi[2 * g.stride + nb] : 0.0};
+        const double h = 0.5 * c.kappa * (d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
         const double k = nnz<L>(i) == 1 ? c.Ef : c.Ff;
 #pragma unroll
-        for (int a = 0; a < L::DIM; a++) {
+        for (int b = 0; b < L::DIM; b++) {
+            const int e = ecomp<L>(i, b);
+            if (e == 0) continue;
+            const double ke = k * e;
 #pragma unroll
-            for (int b = 0; b < L::DIM; b++) {
-                const int e = ecomp<L>(i, b);
-                if (e == 0) continue;
-                f[a] -= (k * e) * T[comp[a][b] * g.stride + nb];
+            for (int a = 0; a < L::DIM; a++) {
+                const double T = c.kappa * d[a] * d[b] - (a == b ? h : 0.0);
+                f[a] -= ke * T;
             }
         }
     }

@@ -68,7 +68,7 @@ void bin_layout(lbm_bin_ctx *c)
     c->o_phi = o; o += align_up(n * 8);
     c->o_vel = o; o += align_up(3 * n * 8);
     const size_t nf = c->p.scheme == LBM_SCHEME_FORCE ? n : 0;  // forcing scheme only
-    c->o_T = o; o += align_up(6 * nf * 8);
+    c->o_T = o; o += align_up(3 * nf * 8);  // d phi
     c->o_force = o; o += align_up(3 * nf * 8);
     c->o_part = o; o += align_up((size_t)RED_BLOCKS * 20 * 8);
     c->o_res = o; o += align_up(32 * 8);
@@ -144,8 +144,8 @@ template <class L, int TX, int TY> void bin_launch_t(lbm_bin_ctx *c, const BinAr
 }
 
 // Forcing scheme: the body force of the current state into the workspace
-// (phi field, stress, divergence); returns the force field, or nullptr for
-// the equilibrium scheme.
+// (phi field, its gradient, the divergence of the stress); returns the force
+// field, or nullptr for the equilibrium scheme.
 const double *bin_body_force(lbm_bin_ctx *c)
 {
     if (c->p.scheme != LBM_SCHEME_FORCE) return nullptr;
@@ -153,11 +153,11 @@ const double *bin_body_force(lbm_bin_ctx *c)
     const Geom g = bin_geom(c);
     if (c->p.lattice == LBM_D2Q9) {
         bin_phi_kernel<D2Q9><<<grid1(c->n), 256, 0, c->stream>>>(g, bin_g(c, c->cur), phi);
-        bin_stress_kernel<D2Q9><<<grid1(c->n), 256, 0, c->stream>>>(g, c->c, phi, T);
+        bin_gradient_kernel<D2Q9><<<grid1(c->n), 256, 0, c->stream>>>(g, c->c, phi, T);
         bin_divergence_kernel<D2Q9><<<grid1(c->n), 256, 0, c->stream>>>(g, c->c, T, force);
     } else {
         bin_phi_kernel<D3Q19><<<grid1(c->n), 256, 0, c->stream>>>(g, bin_g(c, c->cur), phi);
-        bin_stress_kernel<D3Q19><<<grid1(c->n), 256, 0, c->stream>>>(g, c->c, phi, T);
+        bin_gradient_kernel<D3Q19><<<grid1(c->n), 256, 0, c->stream>>>(g, c->c, phi, T);
         bin_divergence_kernel<D3Q19><<<grid1(c->n), 256, 0, c->stream>>>(g, c->c, T, force);
     }
     return force;
