@@ -19,6 +19,12 @@
 // (xderiv), (laplace) and (laplacian3d); both distributions relax by BGK,
 // Eq. (latbolt), with times tau and tau_phi.
 //
+// Forcing scheme (section "Using a forcing method", carried over): the f
+// equilibrium drops the w^ab terms and f receives the forcing terms of the
+// body force g = -div(kappa d phi d phi - delta kappa |d phi|^2 / 2), which
+// three small kernels form before the march (phi, its gradient, the
+// divergence with the force stencil); phi is advected by v = u + g / (2 rho).
+//
 // Storage is FP64 in the pull layout of the liquid-gas kernels: S[i][r]
 // holds the post-collision population of direction i at its source site,
 // and the population arriving at r is S[i][r - e_i].
