@@ -21,9 +21,9 @@
 //
 // Forcing scheme (section "Using a forcing method", carried over): the f
 // equilibrium drops the w^ab terms and f receives the forcing terms of the
-// body force g = -div(kappa d phi d phi - delta kappa |d phi|^2 / 2), which
-// three small kernels form before the march (phi, its gradient, the
-// divergence with the force stencil); phi is advected by v = u + g / (2 rho).
+// body force g = -div(kappa d phi d phi - delta kappa |d phi|^2 / 2); phi is
+// advected by v = u + g / (2 rho).  A step is the phi kernel, then one march
+// (bin_force_step_kernel) that forms the gradient and the force in LDS.
 //
 // Storage is FP64 in the pull layout of the liquid-gas kernels: S[i][r]
 // holds the post-collision population of direction i at its source site,
@@ -75,7 +75,7 @@ struct BinArgs {
     int nx, ny, np;              // in-plane x, in-plane y (1 for D2Q9), planes
     long long stride;            // elements between direction arrays
     int tiles_x, tiles_y, cp;    // tiles per in-plane axis, planes per workgroup
-    const double *__restrict__ force;  // forcing scheme: body force [3][n]
+    const double *__restrict__ phi;    // forcing scheme: phi field [n] of the state
 };
 
 template <class L> __device__ __forceinline__ double bin_grad_coef(const BinCoefs &c, int i)
@@ -228,7 +228,7 @@ __device__ __forceinline__ void wrap3(int v, int n, int (&w)[3])
 // the coordinate a population of offset o arrives from: x - o
 __device__ __forceinline__ int from3(const int (&w)[3], int o) { return o > 0 ? w[1] : (o < 0 ? w[2] : w[0]); }
 
-template <class L, int TX, int TY, bool WALL, bool FORCE = false>
+template <class L, int TX, int TY, bool WALL>
 __global__ __launch_bounds__(TX * TY) void bin_step_kernel(BinArgs a)
 {
     constexpr int Q = L::Q, NT = TX * TY;
@@ -354,21 +354,154 @@ __global__ __launch_bounds__(TX * TY) void bin_step_kernel(BinArgs a)
             double fin[Q];
 #pragma unroll
             for (int i = 0; i < Q; i++) fin[i] = a.fsrc[src_index(rx[0], ry[0], P, i)];
-            double gf[3] = {0.0, 0.0, 0.0};
-            if (FORCE) {
-                gf[0] = a.force[site];
-                gf[1] = a.force[a.stride + site];
-                if (L::DIM == 3) gf[2] = a.force[2 * a.stride + site];
-            }
-            const BinSite st = bin_collide_f<L, FORCE>(a.c, fin, phi, d, lap, [&](int i, double v) {
+            const BinSite st = bin_collide_f<L>(a.c, fin, phi, d, lap, [&](int i, double v) {
                 __builtin_nontemporal_store(v, a.fdst + (long long)i * a.stride + site);
-            }, gf);
+            });
             bin_collide_g<L>(a.c, gcur, st, [&](int i, double v) {
                 __builtin_nontemporal_store(v, a.gdst + (long long)i * a.stride + site);
             });
         }
 #pragma unroll
         for (int i = 0; i < Q; i++) gcur[i] = gnext[i];
+    }
+}
+
+// Forcing scheme, fused: one march per step after the phi kernel (periodic
+// lattices).  Per plane: (1) the phi field of the plane two ahead, with a
+// two-site in-plane halo, into an LDS ring of five planes; barrier; (2) the
+// gradient of phi on the plane ahead, with a one-site halo, into a ring of
+// three planes; barrier; (3) the collision of the current plane: phi and
+// lap(phi) from the phi ring, the body force -sum_b d_b T_ab with the force
+// stencil from the gradients of the neighbours (T_ab = kappa d_a phi d_b phi
+// - delta_ab kappa |d phi|^2 / 2 formed at each), the own f and g pulled.  A
+// plane is written into the phi ring only after every thread has left the
+// collision that last read that slot (five slots, written before the first
+// barrier), and into the gradient ring only after the first barrier of the
+// next plane (three slots).
+template <class L, int TX, int TY>
+__global__ __launch_bounds__(TX * TY) void bin_force_step_kernel(BinArgs a)
+{
+    constexpr int Q = L::Q, NT = TX * TY;
+    constexpr int HY = L::DIM == 3 ? 1 : 0;
+    constexpr int PW2 = TX + 4, PL2 = PW2 * (TY + 4 * HY);  // phi: two-site halo
+    constexpr int PW1 = TX + 2, PL1 = PW1 * (TY + 2 * HY);  // gradient: one-site halo
+    constexpr int N2 = (PL2 + NT - 1) / NT, N1 = (PL1 + NT - 1) / NT;
+    __shared__ double phis[5][PL2];
+    __shared__ double grd[3][3][PL1];
+
+    const int tid = threadIdx.x;
+    int b = blockIdx.x;
+    if (L::DIM == 2 && (gridDim.x & 7) == 0) b = (b & 7) * (gridDim.x >> 3) + (b >> 3);
+    const int bx = b % a.tiles_x;
+    b /= a.tiles_x;
+    const int by = b % a.tiles_y;
+    const int ch = b / a.tiles_y;
+    const int x0 = bx * TX, y0 = by * TY;
+    const int p_begin = ch * a.cp;
+    const int p_end = min(p_begin + a.cp, a.np);
+    const long long nxy = (long long)a.nx * a.ny;
+
+    const int tx = tid % TX, ty = tid / TX;
+    const int x = x0 + tx, y = y0 + ty;
+    const bool own = x < a.nx && y < a.ny;
+    int ox3[3], oy3[3];
+    wrap3(x, a.nx, ox3);
+    wrap3(y, a.ny, oy3);
+    const int c2 = (ty + 2 * HY) * PW2 + tx + 2;  // own entry in the phi ring
+    const int c1 = (ty + HY) * PW1 + tx + 1;      // own entry in the gradient ring
+
+    // in-plane offsets of this thread's phi-ring entries
+    int off2[N2];
+#pragma unroll
+    for (int k = 0; k < N2; k++) {
+        const int e = tid + k * NT;
+        const int wx = wrapg(x0 + e % PW2 - 2, a.nx);
+        const int wy = wrapg(y0 + e / PW2 - 2 * HY, a.ny);
+        off2[k] = e < PL2 ? wy * a.nx + wx : -1;
+    }
+    auto load_phi = [&](int p, int s) {
+        const long long base = (long long)wrapg(p, a.np) * nxy;
+#pragma unroll
+        for (int k = 0; k < N2; k++)
+            if (off2[k] >= 0) phis[s][tid + k * NT] = a.phi[base + off2[k]];
+    };
+    // gradient of the plane in phi slot sc (neighbour planes in sm, sp)
+    auto gradient = [&](int sm, int sc, int sp, int gs) {
+        const double *sl[3] = {phis[sm], phis[sc], phis[sp]};
+#pragma unroll
+        for (int k = 0; k < N1; k++) {
+            const int e = tid + k * NT;
+            if (e >= PL1) continue;
+            const int r2 = (e / PW1 + HY) * PW2 + e % PW1 + 1;  // the entry in phi-ring coordinates
+            double d[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+            for (int i = 1; i < Q; i++) {
+                const double v = bin_grad_coef<L>(a.c, i) * sl[1 + op<L>(i)][r2 + oy<L>(i) * PW2 + ox<L>(i)];
+                if (L::ex[i]) d[0] += L::ex[i] * v;
+                if (L::ey[i]) d[1] += L::ey[i] * v;
+                if (L::ez[i]) d[2] += L::ez[i] * v;
+            }
+            grd[gs][0][e] = d[0];
+            grd[gs][1][e] = d[1];
+            grd[gs][2][e] = d[2];
+        }
+    };
+    // slots: phi of plane q at (q - p_begin + 2) % 5, gradient at (q - p_begin + 1) % 3
+    load_phi(p_begin - 2, 0);
+    load_phi(p_begin - 1, 1);
+    load_phi(p_begin, 2);
+    load_phi(p_begin + 1, 3);
+    __syncthreads();
+    gradient(0, 1, 2, 0);
+    gradient(1, 2, 3, 1);
+    for (int t = 0; p_begin + t < p_end; t++) {
+        const int p = p_begin + t;
+        load_phi(p + 2, (t + 4) % 5);
+        __syncthreads();
+        gradient((t + 2) % 5, (t + 3) % 5, (t + 4) % 5, (t + 2) % 3);
+        __syncthreads();
+        if (!own) continue;
+        const double *sl[3] = {phis[(t + 1) % 5], phis[(t + 2) % 5], phis[(t + 3) % 5]};
+        const int gsl[3] = {t % 3, (t + 1) % 3, (t + 2) % 3};
+        const double phi = sl[1][c2];
+        double lap = 0.0, gf[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int i = 1; i < Q; i++) {
+            lap += bin_lap_coef<L>(a.c, i) * (sl[1 + op<L>(i)][c2 + oy<L>(i) * PW2 + ox<L>(i)] - phi);
+            // -sum_b (force stencil) e_ib T_ab at the neighbour r + e_i
+            const int g = gsl[1 + op<L>(i)], e = c1 + oy<L>(i) * PW1 + ox<L>(i);
+            const double d[3] = {grd[g][0][e], grd[g][1][e], L::DIM == 3 ? grd[g][2][e] : 0.0};
+            const double h = 0.5 * a.c.kappa * (d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+            const double k = nnz<L>(i) == 1 ? a.c.Ef : a.c.Ff;
+#pragma unroll
+            for (int bb = 0; bb < L::DIM; bb++) {
+                const int eb = ecomp<L>(i, bb);
+                if (eb == 0) continue;
+#pragma unroll
+                for (int aa = 0; aa < L::DIM; aa++)
+                    gf[aa] -= (k * eb) * (a.c.kappa * d[aa] * d[bb] - (aa == bb ? h : 0.0));
+            }
+        }
+        int P[3];
+        wrap3(p, a.np, P);
+        auto src = [&](int i) {
+            return (long long)i * a.stride + (long long)from3(P, op<L>(i)) * nxy +
+                   (long long)from3(oy3, oy<L>(i)) * a.nx + from3(ox3, ox<L>(i));
+        };
+        const long long site = (long long)p * nxy + (long long)y * a.nx + x;
+        double fin[Q];
+#pragma unroll
+        for (int i = 0; i < Q; i++) fin[i] = a.fsrc[src(i)];
+        const double dz[3] = {0.0, 0.0, 0.0};  // no w^ab terms in this scheme
+        const BinSite st = bin_collide_f<L, true>(a.c, fin, phi, dz, lap, [&](int i, double v) {
+            __builtin_nontemporal_store(v, a.fdst + (long long)i * a.stride + site);
+        }, gf);
+        double gin[Q];
+#pragma unroll
+        for (int i = 0; i < Q; i++) gin[i] = a.gsrc[src(i)];
+        bin_collide_g<L>(a.c, gin, st, [&](int i, double v) {
+            __builtin_nontemporal_store(v, a.gdst + (long long)i * a.stride + site);
+        });
     }
 }
 
@@ -493,8 +626,8 @@ __global__ void bin_moments_kernel(Geom g, bool wall, const double *__restrict__
     }
 }
 
-// Forcing scheme, before each step: the order parameter phi = sum_i g_i of
-// the arriving populations (periodic lattices) ...
+// Forcing scheme: the order parameter phi = sum_i g_i of the arriving
+// populations (periodic lattices), before each step and for observables ...
 template <class L>
 __global__ void bin_phi_kernel(Geom g, const double *__restrict__ gsrc, double *__restrict__ phi)
 {
@@ -508,7 +641,8 @@ __global__ void bin_phi_kernel(Geom g, const double *__restrict__ gsrc, double *
     phi[s] = v;
 }
 
-// ... the gradient d phi with the gradient stencil, dphi[3][n] ...
+// ... and, for observables (the velocity v = u + g / (2 rho)), the gradient
+// d phi with the gradient stencil, dphi[3][n] ...
 template <class L>
 __global__ void bin_gradient_kernel(Geom g, BinCoefs c, const double *__restrict__ phi,
                                     double *__restrict__ dphi)

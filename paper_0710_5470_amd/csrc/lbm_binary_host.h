@@ -136,16 +136,16 @@ int bin_default_planes(const lbm_bin_ctx *c, int tile)
 template <class L, int TX, int TY> void bin_launch_t(lbm_bin_ctx *c, const BinArgs &a, int nblk)
 {
     if (c->p.scheme == LBM_SCHEME_FORCE)
-        bin_step_kernel<L, TX, TY, false, true><<<nblk, TX * TY, 0, c->stream>>>(a);
+        bin_force_step_kernel<L, TX, TY><<<nblk, TX * TY, 0, c->stream>>>(a);
     else if (c->p.wall)
         bin_step_kernel<L, TX, TY, true><<<nblk, TX * TY, 0, c->stream>>>(a);
     else
         bin_step_kernel<L, TX, TY, false><<<nblk, TX * TY, 0, c->stream>>>(a);
 }
 
-// Forcing scheme: the body force of the current state into the workspace
-// (phi field, its gradient, the divergence of the stress); returns the force
-// field, or nullptr for the equilibrium scheme.
+// Forcing scheme, for observables: the body force of the current state into
+// the workspace (phi field, its gradient, the divergence of the stress);
+// returns the force field, or nullptr for the equilibrium scheme.
 const double *bin_body_force(lbm_bin_ctx *c)
 {
     if (c->p.scheme != LBM_SCHEME_FORCE) return nullptr;
@@ -178,7 +178,15 @@ void bin_launch_step(lbm_bin_ctx *c)
     int chunks;
     bin_grid(c, c->tile, c->cp, a.tiles_x, a.tiles_y, chunks);
     a.cp = c->cp;
-    a.force = bin_body_force(c);
+    if (c->p.scheme == LBM_SCHEME_FORCE) {
+        // the phi field of the state; the march forms gradient and force itself
+        double *phi = bws(c, c->o_phi);
+        if (c->p.lattice == LBM_D2Q9)
+            bin_phi_kernel<D2Q9><<<grid1(c->n), 256, 0, c->stream>>>(bin_geom(c), bin_g(c, c->cur), phi);
+        else
+            bin_phi_kernel<D3Q19><<<grid1(c->n), 256, 0, c->stream>>>(bin_geom(c), bin_g(c, c->cur), phi);
+        a.phi = phi;
+    }
     const int nblk = a.tiles_x * a.tiles_y * chunks;
     if (c->p.lattice == LBM_D2Q9) {
         if (c->tile == 0) bin_launch_t<D2Q9, 128, 1>(c, a, nblk);
