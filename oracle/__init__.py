@@ -64,12 +64,21 @@ OPTIMUM = dict(B=1.0 / 12.0, D=1.0 / 6.0, F=1.0 / 12.0,
                wp_d=1.0 / 12.0, wt_d=1.0 / 12.0, wxx_d=-1.0 / 24.0)
 
 
+# D3Q15 (lattice comparison only): corner stencil coefficients with an
+# isotropic leading error (B = 1/24, D = 1/12), corner w^p and w^t weights
+# 1/24 (the same isotropy), and the corner w^xx weight c (wxx_d); the
+# second-moment conditions fix the face weights from the corner ones.
+D3Q15_DEFAULT = dict(B=1.0 / 24.0, D=1.0 / 12.0, wp_d=1.0 / 24.0, wt_d=1.0 / 24.0, wxx_d=0.0)
+
+
 def params(q=9, scheme=0, shape=(64, 64), a=9 / 49, b=2 / 21, T=0.5, kappa=0.01,
            tau=1.0, lambda_on=1, **over):
     """shape is (nx, ny) for D2Q9 or (nx, ny, nz) for D3Q19."""
     nx, ny = shape[0], shape[1]
     nz = shape[2] if len(shape) > 2 else 1
     kw = dict(OPTIMUM)
+    if q == 15:
+        kw.update(D3Q15_DEFAULT)
     kw.update(over)
     return OrcParams(q, scheme, nx, ny, nz, lambda_on, a, b, T, kappa, tau,
                      kw["B"], kw["D"], kw["F"], kw["wp_d"], kw["wt_d"], kw["wxx_d"])

@@ -66,6 +66,15 @@ static const int E2[9][3] = {
     {0, 0, 0}, {1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0},
     {1, 1, 0}, {-1, -1, 0}, {-1, 1, 0}, {1, -1, 0}};
 
+/* D3Q15 (for the lattice comparison; the paper gives no D3Q15 tables):
+ * the faces e1..e6 as in D3Q19, then the eight cube corners in opposite
+ * pairs. */
+static const int E15[15][3] = {
+    {0, 0, 0},
+    {1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1},
+    {1, 1, 1}, {-1, -1, -1}, {1, 1, -1}, {-1, -1, 1},
+    {1, -1, 1}, {-1, 1, -1}, {-1, 1, 1}, {1, -1, -1}};
+
 /* D3Q19 numbering of Section "Extension to 3D": faces e1..e6, then the
  * twelve square diagonals e7..e18 column by column as printed. */
 static const int E3[19][3] = {
@@ -149,6 +158,65 @@ static void build_tables(const orc_params *p, tables *t)
     memset(t, 0, sizeof(*t));
     t->q = p->q;
     t->dim = (p->q == 9) ? 2 : 3;
+    if (p->q == 15) {
+        /* D3Q15, built as the paper builds D3Q19 (the paper gives no D3Q15
+         * tables): the scalar terms on weights with sum w e_a e_b = delta_ab
+         * (w: faces 1/3, corners 1/24, the isotropic fourth moment; w^p, w^t
+         * with corner weights wp_d, wt_d, 1/24 for the same isotropy); the
+         * kappa d_a d_b terms on weights meeting the second-moment conditions
+         * of Appendix A (w^xx: x faces 1/4 - 4c, other faces -1/4 - 4c,
+         * corners c, c free and passed as wxx_d; w^xy = e_x e_y / 8 on the
+         * corners, the only velocities with e_x e_y != 0); the stencils on
+         * faces and corners, B and D the corner coefficients (2A + 8B = 1,
+         * C + 4D = 1 as for D3Q19; B = 1/24, D = 1/12 make their leading
+         * error isotropic). */
+        memcpy(t->e, E15, sizeof(E15));
+        for (int i = 1; i <= 14; i++) {
+            t->w[i] = (i <= 6) ? 1.0 / 3.0 : 1.0 / 24.0;
+            /* w^p, w^t: corner weight wp_d / wt_d, faces from 2 w_f + 8 w_c = 1 */
+            t->wp[i] = (i <= 6) ? 0.5 - 4.0 * p->wp_d : p->wp_d;
+            t->wt[i] = (i <= 6) ? 0.5 - 4.0 * p->wt_d : p->wt_d;
+        }
+        const double c = p->wxx_d;
+        for (int i = 1; i <= 14; i++) {
+            const int *e = E15[i];
+            for (int a = 0; a < 3; a++) {
+                if (i <= 6) /* faces: along a, or not */
+                    t->wm[a][i] = (e[a] != 0) ? 0.25 - 4.0 * c : -0.25 - 4.0 * c;
+                else
+                    t->wm[a][i] = c;
+            }
+            if (i > 6) {
+                t->wm[3][i] = 0.125 * e[0] * e[1];
+                t->wm[4][i] = 0.125 * e[1] * e[2];
+                t->wm[5][i] = 0.125 * e[2] * e[0];
+            }
+        }
+        const double A = (1.0 - 8.0 * p->B) / 2.0, C = 1.0 - 4.0 * p->D;
+        zero3(t->gx); zero3(t->gy); zero3(t->gz); zero3(t->lap);
+        for (int sl = 0; sl < 3; sl++)
+            for (int r = 0; r < 3; r++)
+                for (int cc = 0; cc < 3; cc++) {
+                    int dx = cc - 1, dy = 1 - r, dz = 1 - sl;
+                    int nnz = (dx != 0) + (dy != 0) + (dz != 0);
+                    if (nnz == 1) {
+                        t->gx[sl][r][cc] = A * dx;
+                        t->gy[sl][r][cc] = A * dy;
+                        t->gz[sl][r][cc] = A * dz;
+                        t->lap[sl][r][cc] = C;
+                    } else if (nnz == 3) {
+                        t->gx[sl][r][cc] = p->B * dx;
+                        t->gy[sl][r][cc] = p->B * dy;
+                        t->gz[sl][r][cc] = p->B * dz;
+                        t->lap[sl][r][cc] = p->D;
+                    }
+                }
+        t->lap[1][1][1] = -(6.0 * C + 8.0 * p->D);
+        memcpy(t->fx, t->gx, sizeof(t->gx)); /* no forcing scheme on D3Q15 */
+        memcpy(t->fy, t->gy, sizeof(t->gy));
+        memcpy(t->fz, t->gz, sizeof(t->gz));
+        return;
+    }
     if (t->dim == 2) {
         memcpy(t->e, E2, sizeof(E2));
         for (int i = 1; i <= 8; i++) t->w[i] = (i <= 4) ? 1.0 / 3.0 : 1.0 / 12.0;
@@ -525,8 +593,9 @@ static void step_t(const orc_params *p, const tables *t, const double *f, double
 /* Advance f (in place) by nsteps. Returns 0, or -1 on a bad argument. */
 int orc_run(const orc_params *p, double *f, int nsteps)
 {
-    if (!(p->q == 9 || p->q == 19) || nsteps < 0) return -1;
+    if (!(p->q == 9 || p->q == 19 || p->q == 15) || nsteps < 0) return -1;
     if (p->q == 9 && p->nz != 1) return -1;
+    if (p->q == 15 && p->scheme != 0) return -1; /* equilibrium scheme only */
     tables t;
     build_tables(p, &t);
     long n = nsites(p);
@@ -750,7 +819,7 @@ static long bin_sidx(const orc_bin_params *bp, int x, int y, int z)
 {
     const orc_params *p = &bp->base;
     if (bp->wall) {
-        if (p->q == 19) {
+        if (p->q != 9) {
             if (z < 0) z = -1 - z;
             else if (z >= p->nz) z = 2 * p->nz - 1 - z;
         } else {
@@ -766,7 +835,7 @@ static int bin_beyond(const orc_bin_params *bp, int y, int z)
 {
     const orc_params *p = &bp->base;
     if (!bp->wall) return 0;
-    return p->q == 19 ? (z < 0 || z >= p->nz) : (y < 0 || y >= p->ny);
+    return p->q != 9 ? (z < 0 || z >= p->nz) : (y < 0 || y >= p->ny);
 }
 
 static int opposite(const tables *t, int i)
@@ -872,10 +941,11 @@ static void geq_bin_site_t(const orc_bin_params *bp, const tables *t, double phi
 static int bin_valid(const orc_bin_params *bp)
 {
     const orc_params *p = &bp->base;
-    if (!(p->q == 9 || p->q == 19)) return 0;
+    if (!(p->q == 9 || p->q == 19 || p->q == 15)) return 0;
     if (p->q == 9 && p->nz != 1) return 0;
     if (p->scheme != 0 && p->scheme != 1) return 0;
     if (p->scheme == 1 && bp->wall) return 0;
+    if (p->q == 15 && p->scheme != 0) return 0; /* D3Q15: tuned equilibrium only */
     return p->nx > 0 && p->ny > 0 && p->nz > 0;
 }
 
@@ -1027,7 +1097,7 @@ int orc_bin_totals(const orc_bin_params *bp, const double *f, const double *g, d
     orc_totals(&bp->base, f, mass, mom);
     const orc_params *p = &bp->base;
     long n = nsites(p);
-    int q = (p->q == 9) ? 9 : 19;
+    int q = p->q;
     double s = 0.0;
     for (int i = 0; i < q; i++)
         for (long k = 0; k < n; k++) s += g[i * n + k];
