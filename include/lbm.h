@@ -50,7 +50,7 @@ extern "C" {
 
 typedef struct lbm_ctx lbm_ctx;
 
-enum { LBM_D2Q9 = 9, LBM_D3Q19 = 19 };
+enum { LBM_D2Q9 = 9, LBM_D3Q19 = 19, LBM_D3Q15 = 15 /* binary stepper only */ };
 enum { LBM_SCHEME_EQ = 0, LBM_SCHEME_FORCE = 1 };
 /* FP64 populations, or FP32 deviations delta_i = f_i - s_i from a fixed
  * per-direction shift s_i (arithmetic in FP32, reductions in FP64). */
@@ -400,7 +400,16 @@ typedef struct {
     double kappa;         /* square-gradient coefficient, >= 0                     */
     double gamma;         /* mobility coefficient of the mu term, >= 0             */
     double tau, tau_phi;  /* relaxation times of f and g, Eq. (latbolt); > 1/2     */
-    int lattice;          /* LBM_D2Q9 or LBM_D3Q19                                 */
+    /* LBM_D2Q9, LBM_D3Q19, or LBM_D3Q15 for the lattice comparison of
+     * section "Extension to 3D" (which gives no D3Q15 tables): faces e1..e6,
+     * then the eight corners in opposite pairs; weights with the moments of
+     * Appendix A, w = faces 1/3, corners 1/24; w^p, w^t corner weights
+     * wp_diag, wt_diag (faces 1/2 - 4 corner; default 1/24), w^xx corner
+     * weight wxx_diag = c (faces along x 1/4 - 4c, others -1/4 - 4c;
+     * default 0), w^xy = e_x e_y / 8; stencil corner coefficients B, D
+     * (2A + 8B = 1, C + 4D = 1; defaults 1/24, 1/12).  Equilibrium scheme
+     * only. */
+    int lattice;
     int nx, ny, nz;       /* lattice extent; nz = 1 for D2Q9                       */
     /* 0: periodic.  1: walls at both ends of the marching axis (y for D2Q9,
      * z for D3Q19), halfway between planes (at -1/2 and n - 1/2): a
@@ -420,7 +429,8 @@ typedef struct {
     /* Stencil and weight overrides as in lbm_params (NaN = the paper's
      * optimum): B, D the gradient and Laplacian off-axis coefficients;
      * wp_diag, wt_diag, wxx_diag the D2Q9 weights w^p_5-8, w^t_5-8,
-     * w^xx_5-8 (NaN for D3Q19).  The gamma mu term of g uses the same w^p. */
+     * w^xx_5-8 (NaN for D3Q19; the corner weights for D3Q15).  The
+     * gamma mu term of g uses the same w^p. */
     double B, D;
     double wp_diag, wt_diag, wxx_diag;
     int tile;             /* launch shape id (lbm_bin_tile_count); -1 = default    */

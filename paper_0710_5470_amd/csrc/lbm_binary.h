@@ -52,6 +52,24 @@
 
 namespace lbm {
 
+// D3Q15, for the lattice comparison of section "Extension to 3D" (binary
+// stepper only): the faces e1..e6 as in D3Q19, then the eight cube corners
+// in opposite pairs.  The paper gives no D3Q15 tables; the host builds them
+// as the paper builds D3Q19 (moments of Appendix A, isotropic leading
+// error where a choice remains, free corner weights overridable).
+struct D3Q15 {
+    static constexpr int Q = 15;
+    static constexpr int DIM = 3;
+    static constexpr int ex[15] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, -1, 1};
+    static constexpr int ey[15] = {0, 0, 0, 1, -1, 0, 0, 1, -1, 1, -1, -1, 1, 1, -1};
+    static constexpr int ez[15] = {0, 0, 0, 0, 0, 1, -1, 1, -1, -1, 1, 1, -1, 1, -1};
+};
+
+// weight of the off-diagonal kappa d_a d_b terms: e_a e_b / 4 on the D2Q9
+// diagonals and D3Q19 edges (the constraint list after Eq. (fi)), e_a e_b / 8
+// on the D3Q15 corners (eight of them carry each pair a, b)
+template <class L> __host__ __device__ constexpr double bin_wxy() { return L::Q == 15 ? 0.125 : 0.25; }
+
 struct BinCoefs {
     double A, B;                 // gradient stencil: on-axis, off-axis
     double C, D;                 // Laplacian stencil: on-axis, off-axis
@@ -99,9 +117,9 @@ template <class L> __device__ __forceinline__ double bin_m_terms(const BinCoefs 
         m += (axis ? (touches ? c.wm_para : c.wm_perp) : (touches ? c.wm_in : c.wm_out)) * M[a];
     }
     const int e0 = L::ex[i], e1 = L::ey[i], e2 = L::ez[i];
-    if (e0 * e1 != 0) m += (0.25 * e0 * e1) * M[3];
-    if (e1 * e2 != 0) m += (0.25 * e1 * e2) * M[4];
-    if (e2 * e0 != 0) m += (0.25 * e2 * e0) * M[5];
+    if (e0 * e1 != 0) m += (bin_wxy<L>() * e0 * e1) * M[3];
+    if (e1 * e2 != 0) m += (bin_wxy<L>() * e1 * e2) * M[4];
+    if (e2 * e0 != 0) m += (bin_wxy<L>() * e2 * e0) * M[5];
     return m;
 }
 

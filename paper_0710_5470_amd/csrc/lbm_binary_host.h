@@ -31,10 +31,19 @@ constexpr int BNT3 = sizeof(BIN_TILES_3D) / sizeof(BIN_TILES_3D[0]);
 TileShape bin_tile(int lattice, int k) { return lattice == LBM_D2Q9 ? BIN_TILES_2D[k] : BIN_TILES_3D[k]; }
 int bin_tile_count(int lattice) { return lattice == LBM_D2Q9 ? BNT2 : BNT3; }
 
+// call f with a value of the velocity-set type of `lattice`
+template <class F> void bin_dispatch(int lattice, F &&f)
+{
+    if (lattice == LBM_D2Q9) f(D2Q9{});
+    else if (lattice == LBM_D3Q19) f(D3Q19{});
+    else f(D3Q15{});
+}
+
 bool bin_valid(const lbm_bin_params *p)
 {
     if (!p) return false;
-    if (p->lattice != LBM_D2Q9 && p->lattice != LBM_D3Q19) return false;
+    if (p->lattice != LBM_D2Q9 && p->lattice != LBM_D3Q19 && p->lattice != LBM_D3Q15) return false;
+    if (p->lattice == LBM_D3Q15 && p->scheme != LBM_SCHEME_EQ) return false;
     if (p->nx < 1 || p->ny < 1 || p->nz < 1) return false;
     if (p->lattice == LBM_D2Q9 && p->nz != 1) return false;
     if ((double)p->nx * p->ny * p->nz * p->lattice >= 4294967296.0) return false;
@@ -83,6 +92,32 @@ double *bin_g(lbm_bin_ctx *c, int which) { return bws(c, which ? c->o_gb : c->o_
 // weights (summary / Eq. (3dres)): the paper's optimum unless overridden.
 BinCoefs bin_coefs(const lbm_bin_params *p)
 {
+    if (p->lattice == LBM_D3Q15) {
+        // D3Q15 (see the header): corner coefficients, faces from the moments
+        BinCoefs c{};
+        c.B = pick(p->B, 1.0 / 24.0);
+        c.D = pick(p->D, 1.0 / 12.0);
+        c.A = (1.0 - 8.0 * c.B) / 2.0;  // 2A + 8B = 1
+        c.C = 1.0 - 4.0 * c.D;          // C + 4D = 1
+        c.w_ax = 1.0 / 3.0;
+        c.w_off = 1.0 / 24.0;
+        c.wp_off = pick(p->wp_diag, 1.0 / 24.0);
+        c.wp_ax = 0.5 - 4.0 * c.wp_off;
+        c.wt_off = pick(p->wt_diag, 1.0 / 24.0);
+        c.wt_ax = 0.5 - 4.0 * c.wt_off;
+        const double wc = pick(p->wxx_diag, 0.0);
+        c.wm_para = 0.25 - 4.0 * wc;
+        c.wm_perp = -0.25 - 4.0 * wc;
+        c.wm_in = wc;
+        c.wm_out = 0.0;
+        c.kappa = p->kappa;
+        c.omega = 1.0 / p->tau;
+        c.omega_g = 1.0 / p->tau_phi;
+        c.pa = p->phi_a;
+        c.pb = p->phi_b;
+        c.gamma = p->gamma;
+        return c;
+    }
     lbm_params q;
     lbm_params_default(&q);
     q.lattice = p->lattice;
@@ -135,9 +170,12 @@ int bin_default_planes(const lbm_bin_ctx *c, int tile)
 
 template <class L, int TX, int TY> void bin_launch_t(lbm_bin_ctx *c, const BinArgs &a, int nblk)
 {
-    if (c->p.scheme == LBM_SCHEME_FORCE)
-        bin_force_step_kernel<L, TX, TY><<<nblk, TX * TY, 0, c->stream>>>(a);
-    else if (c->p.wall)
+    if constexpr (L::Q != 15)  // no forcing scheme on D3Q15
+        if (c->p.scheme == LBM_SCHEME_FORCE) {
+            bin_force_step_kernel<L, TX, TY><<<nblk, TX * TY, 0, c->stream>>>(a);
+            return;
+        }
+    if (c->p.wall)
         bin_step_kernel<L, TX, TY, true><<<nblk, TX * TY, 0, c->stream>>>(a);
     else
         bin_step_kernel<L, TX, TY, false><<<nblk, TX * TY, 0, c->stream>>>(a);
@@ -151,15 +189,14 @@ const double *bin_body_force(lbm_bin_ctx *c)
     if (c->p.scheme != LBM_SCHEME_FORCE) return nullptr;
     double *phi = bws(c, c->o_phi), *T = bws(c, c->o_T), *force = bws(c, c->o_force);
     const Geom g = bin_geom(c);
-    if (c->p.lattice == LBM_D2Q9) {
-        bin_phi_kernel<D2Q9><<<grid1(c->n), 256, 0, c->stream>>>(g, bin_g(c, c->cur), phi);
-        bin_gradient_kernel<D2Q9><<<grid1(c->n), 256, 0, c->stream>>>(g, c->c, phi, T);
-        bin_divergence_kernel<D2Q9><<<grid1(c->n), 256, 0, c->stream>>>(g, c->c, T, force);
-    } else {
-        bin_phi_kernel<D3Q19><<<grid1(c->n), 256, 0, c->stream>>>(g, bin_g(c, c->cur), phi);
-        bin_gradient_kernel<D3Q19><<<grid1(c->n), 256, 0, c->stream>>>(g, c->c, phi, T);
-        bin_divergence_kernel<D3Q19><<<grid1(c->n), 256, 0, c->stream>>>(g, c->c, T, force);
-    }
+    bin_dispatch(c->p.lattice, [&](auto l) {
+        using L = decltype(l);
+        if constexpr (L::Q != 15) {
+            bin_phi_kernel<L><<<grid1(c->n), 256, 0, c->stream>>>(g, bin_g(c, c->cur), phi);
+            bin_gradient_kernel<L><<<grid1(c->n), 256, 0, c->stream>>>(g, c->c, phi, T);
+            bin_divergence_kernel<L><<<grid1(c->n), 256, 0, c->stream>>>(g, c->c, T, force);
+        }
+    });
     return force;
 }
 
@@ -181,33 +218,35 @@ void bin_launch_step(lbm_bin_ctx *c)
     if (c->p.scheme == LBM_SCHEME_FORCE) {
         // the phi field of the state; the march forms gradient and force itself
         double *phi = bws(c, c->o_phi);
-        if (c->p.lattice == LBM_D2Q9)
-            bin_phi_kernel<D2Q9><<<grid1(c->n), 256, 0, c->stream>>>(bin_geom(c), bin_g(c, c->cur), phi);
-        else
-            bin_phi_kernel<D3Q19><<<grid1(c->n), 256, 0, c->stream>>>(bin_geom(c), bin_g(c, c->cur), phi);
+        bin_dispatch(c->p.lattice, [&](auto l) {
+            using L = decltype(l);
+            if constexpr (L::Q != 15)
+                bin_phi_kernel<L><<<grid1(c->n), 256, 0, c->stream>>>(bin_geom(c), bin_g(c, c->cur), phi);
+        });
         a.phi = phi;
     }
     const int nblk = a.tiles_x * a.tiles_y * chunks;
-    if (c->p.lattice == LBM_D2Q9) {
-        if (c->tile == 0) bin_launch_t<D2Q9, 128, 1>(c, a, nblk);
-        else bin_launch_t<D2Q9, 256, 1>(c, a, nblk);
-    } else {
-        if (c->tile == 0) bin_launch_t<D3Q19, 32, 8>(c, a, nblk);
-        else if (c->tile == 1) bin_launch_t<D3Q19, 64, 4>(c, a, nblk);
-        else if (c->tile == 2) bin_launch_t<D3Q19, 64, 8>(c, a, nblk);
-        else bin_launch_t<D3Q19, 128, 4>(c, a, nblk);
-    }
+    bin_dispatch(c->p.lattice, [&](auto l) {
+        using L = decltype(l);
+        if constexpr (L::DIM == 2) {
+            if (c->tile == 0) bin_launch_t<L, 128, 1>(c, a, nblk);
+            else bin_launch_t<L, 256, 1>(c, a, nblk);
+        } else {
+            if (c->tile == 0) bin_launch_t<L, 32, 8>(c, a, nblk);
+            else if (c->tile == 1) bin_launch_t<L, 64, 4>(c, a, nblk);
+            else if (c->tile == 2) bin_launch_t<L, 64, 8>(c, a, nblk);
+            else bin_launch_t<L, 128, 4>(c, a, nblk);
+        }
+    });
 }
 
 void bin_launch_moments(lbm_bin_ctx *c, double *rho, double *phi, double *vel)
 {
     const double *force = vel ? bin_body_force(c) : nullptr;
-    if (c->p.lattice == LBM_D2Q9)
-        bin_moments_kernel<D2Q9><<<grid1(c->n), 256, 0, c->stream>>>(
+    bin_dispatch(c->p.lattice, [&](auto l) {
+        bin_moments_kernel<decltype(l)><<<grid1(c->n), 256, 0, c->stream>>>(
             bin_geom(c), c->p.wall, bin_f(c, c->cur), bin_g(c, c->cur), force, rho, phi, vel);
-    else
-        bin_moments_kernel<D3Q19><<<grid1(c->n), 256, 0, c->stream>>>(
-            bin_geom(c), c->p.wall, bin_f(c, c->cur), bin_g(c, c->cur), force, rho, phi, vel);
+    });
 }
 
 // reduce (rho, vel) into out[OBS_NV] (b = 0: a site is bad if non-finite or rho <= 0)
@@ -361,13 +400,11 @@ int lbm_bin_init(lbm_bin_ctx **out, const lbm_bin_params *p, void *dev_workspace
     const Geom g = bin_geom(c);
     const unsigned nb = grid1(c->n);
     double *f0 = bin_f(c, 0), *g0 = bin_g(c, 0);
-    if (p->lattice == LBM_D2Q9) {
-        if (force) bin_init_kernel<D2Q9, true><<<nb, 256, 0, c->stream>>>(g, c->c, p->wall, dev_rho0, dev_phi0, dev_u0, f0, g0);
-        else bin_init_kernel<D2Q9, false><<<nb, 256, 0, c->stream>>>(g, c->c, p->wall, dev_rho0, dev_phi0, dev_u0, f0, g0);
-    } else {
-        if (force) bin_init_kernel<D3Q19, true><<<nb, 256, 0, c->stream>>>(g, c->c, p->wall, dev_rho0, dev_phi0, dev_u0, f0, g0);
-        else bin_init_kernel<D3Q19, false><<<nb, 256, 0, c->stream>>>(g, c->c, p->wall, dev_rho0, dev_phi0, dev_u0, f0, g0);
-    }
+    bin_dispatch(p->lattice, [&](auto l) {
+        using L = decltype(l);
+        if (force) bin_init_kernel<L, true><<<nb, 256, 0, c->stream>>>(g, c->c, p->wall, dev_rho0, dev_phi0, dev_u0, f0, g0);
+        else bin_init_kernel<L, false><<<nb, 256, 0, c->stream>>>(g, c->c, p->wall, dev_rho0, dev_phi0, dev_u0, f0, g0);
+    });
     if (hipGetLastError() != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess) {
         delete c;
         return LBM_E_DEVICE;
@@ -393,10 +430,9 @@ int lbm_bin_moments(lbm_bin_ctx *c, double *dev_rho, double *dev_phi, double *de
     double *ph = dev_phi ? dev_phi : (dev_mu ? bws(c, c->o_phi) : nullptr);
     bin_launch_moments(c, dev_rho, ph, dev_vel);
     if (dev_mu) {
-        if (c->p.lattice == LBM_D2Q9)
-            bin_mu_kernel<D2Q9><<<grid1(c->n), 256, 0, c->stream>>>(bin_geom(c), c->c, c->p.wall, ph, dev_mu);
-        else
-            bin_mu_kernel<D3Q19><<<grid1(c->n), 256, 0, c->stream>>>(bin_geom(c), c->c, c->p.wall, ph, dev_mu);
+        bin_dispatch(c->p.lattice, [&](auto l) {
+            bin_mu_kernel<decltype(l)><<<grid1(c->n), 256, 0, c->stream>>>(bin_geom(c), c->c, c->p.wall, ph, dev_mu);
+        });
     }
     return hipGetLastError() == hipSuccess ? LBM_OK : LBM_E_DEVICE;
 }
@@ -417,23 +453,22 @@ int lbm_bin_max_spurious_u(lbm_bin_ctx *c, double *host_out)
 int lbm_bin_invariants(lbm_bin_ctx *c, double *host_mass, double *host_phi, double *host_mom)
 {
     if (!c) return LBM_E_INVAL;
-    return c->p.lattice == LBM_D2Q9 ? bin_totals_t<D2Q9>(c, host_mass, host_phi, host_mom)
-                                    : bin_totals_t<D3Q19>(c, host_mass, host_phi, host_mom);
+    int rc = LBM_OK;
+    bin_dispatch(c->p.lattice, [&](auto l) { rc = bin_totals_t<decltype(l)>(c, host_mass, host_phi, host_mom); });
+    return rc;
 }
 
 int lbm_bin_get_state(lbm_bin_ctx *c, double *dev_f, double *dev_g)
 {
     if (!c || !dev_f || !dev_g) return LBM_E_INVAL;
-    if (c->p.lattice == LBM_D2Q9) bin_state_io_t<D2Q9>(c, dev_f, dev_g, nullptr, nullptr);
-    else bin_state_io_t<D3Q19>(c, dev_f, dev_g, nullptr, nullptr);
+    bin_dispatch(c->p.lattice, [&](auto l) { bin_state_io_t<decltype(l)>(c, dev_f, dev_g, nullptr, nullptr); });
     return hipGetLastError() == hipSuccess ? LBM_OK : LBM_E_DEVICE;
 }
 
 int lbm_bin_set_state(lbm_bin_ctx *c, const double *dev_f, const double *dev_g)
 {
     if (!c || !dev_f || !dev_g) return LBM_E_INVAL;
-    if (c->p.lattice == LBM_D2Q9) bin_state_io_t<D2Q9>(c, nullptr, nullptr, dev_f, dev_g);
-    else bin_state_io_t<D3Q19>(c, nullptr, nullptr, dev_f, dev_g);
+    bin_dispatch(c->p.lattice, [&](auto l) { bin_state_io_t<decltype(l)>(c, nullptr, nullptr, dev_f, dev_g); });
     return hipGetLastError() == hipSuccess ? LBM_OK : LBM_E_DEVICE;
 }
 
@@ -441,7 +476,7 @@ long long lbm_bin_steps_done(const lbm_bin_ctx *c) { return c ? c->steps : -1; }
 
 int lbm_bin_tile_count(int lattice)
 {
-    if (lattice != LBM_D2Q9 && lattice != LBM_D3Q19) return LBM_E_INVAL;
+    if (lattice != LBM_D2Q9 && lattice != LBM_D3Q19 && lattice != LBM_D3Q15) return LBM_E_INVAL;
     return bin_tile_count(lattice);
 }
 

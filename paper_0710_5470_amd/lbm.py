@@ -17,6 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("LBM_LIBRARY", os.path.join(_HERE, "_lib", "liblbm.so"))
 
 D2Q9, D3Q19 = 9, 19
+D3Q15 = 15  # binary stepper only (lattice comparison)
 SCHEME_EQ, SCHEME_FORCE = 0, 1
 STORE_F64, STORE_F32_SHIFTED = 0, 1
 SHIFT_REST_EQ, SHIFT_WEIGHTS = 0, 1

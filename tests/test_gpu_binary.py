@@ -66,6 +66,10 @@ def _gpu_run(gp, rho, phi, u, nsteps, tile=-1, planes=0):
     return sim, f, g, obs
 
 
+# D3Q15 corner weights that keep the tuned equilibrium stable at these
+# parameters: w^t = w^p = 1/8 on the corners, w^xx corner -1/32, B = 1/12
+Q15 = dict(wt_diag=1 / 8, wp_diag=1 / 8, wxx_diag=-1 / 32, B=1 / 12)
+
 CASES = [
     (9, (64, 48), 120, {}), (9, (37, 29), 80, dict(tau=0.8, tau_phi=1.3, gamma=0.7)),
     (9, (300, 5), 40, {}), (9, (33, 2), 30, {}), (9, (5, 3), 20, {}),
@@ -85,6 +89,10 @@ CASES = [
     (9, (5, 3), 20, dict(scheme=1)), (19, (24, 20, 18), 40, dict(scheme=1)),
     (19, (37, 11, 9), 30, dict(scheme=1, tau=0.7, tau_phi=1.2, gamma=0.8)),
     (19, (13, 9, 2), 20, dict(scheme=1)), (19, (16, 12, 1), 20, dict(scheme=1)),
+    # D3Q15 (the lattice comparison): the stable choice of the free corner
+    # weights, and a short run with the isotropic defaults
+    (15, (24, 20, 18), 40, Q15), (15, (37, 11, 9), 30, dict(Q15, tau=0.8, tau_phi=1.2)),
+    (15, (13, 9, 2), 20, dict(Q15, wall=1)), (15, (20, 13, 9), 10, {}),
 ]
 
 
@@ -120,10 +128,11 @@ def test_binary_matches_oracle(q, shape, nsteps, kw):
 
 @pytest.mark.parametrize("q,shape,wall,scheme", [(9, (200, 37), 0, 0), (19, (70, 21, 13), 0, 0),
                                                  (9, (130, 21), 1, 0), (19, (70, 21, 13), 1, 0),
-                                                 (9, (130, 21), 0, 1), (19, (70, 21, 13), 0, 1)])
+                                                 (9, (130, 21), 0, 1), (19, (70, 21, 13), 0, 1),
+                                                 (15, (70, 21, 13), 0, 0)])
 def test_binary_launch_shapes_agree_bitwise(q, shape, wall, scheme):
     lbm = _lbm()
-    gp, _ = _pair(q, shape, tau=0.9, tau_phi=1.2, wall=wall, scheme=scheme)
+    gp, _ = _pair(q, shape, tau=0.9, tau_phi=1.2, wall=wall, scheme=scheme, **(Q15 if q == 15 else {}))
     rho, phi, u = _fields(shape)
     ref = None
     for tile in range(lbm.lbm_bin_tile_count(q)):
@@ -348,3 +357,25 @@ def test_forcing_scheme_lowers_binary_spurious_velocities(q, n, radius):
     _say("binary drop q", q, "max|v| after 10000 steps: equilibrium", umax[0], "forcing", umax[1])
     assert np.isfinite(umax[1]) and umax[1] > 0
     assert 2 * umax[1] < umax[0]
+
+
+def test_d3q15_leaves_larger_binary_spurious_velocities_than_d3q19():
+    """Section "Extension to 3D": 19 velocities are necessary.  A binary drop
+    (R = 10 on 32^3, 2000 steps) on D3Q19 at the paper's weights against
+    D3Q15 with the stable choice of its free corner weights (the isotropic
+    D3Q15 choice is unstable here; the oracle measured 6.7x)."""
+    from paper_0710_5470_amd import inputs
+    lbm = _lbm()
+    n = 32
+    phi = inputs.tanh_drop((n, n, n), 10.0, 1.0, -1.0, 2.0).reshape(-1)
+    rho = np.ones_like(phi)
+    umax = {}
+    for q, kw in ((19, {}), (15, Q15)):
+        gp, _ = _pair(q, (n, n, n), **kw)
+        sim = lbm.BinarySimulation(gp, rho, phi)
+        sim.step(2000)
+        umax[q] = sim.max_spurious_u()
+        sim.close()
+    _say("binary drop 32^3 max|u| after 2000 steps: D3Q19", umax[19], "D3Q15", umax[15])
+    assert np.isfinite(umax[15])
+    assert umax[15] > 4 * umax[19]
