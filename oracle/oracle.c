@@ -838,6 +838,69 @@ static int bin_beyond(const orc_bin_params *bp, int y, int z)
     return p->q != 9 ? (z < 0 || z >= p->nz) : (y < 0 || y >= p->ny);
 }
 
+/* Site index with the bounded axis reflected to any depth: the fluid is
+ * continued beyond each wall as its mirror image, so along that axis the
+ * continuation has period 2n. */
+static long bin_ridx(const orc_bin_params *bp, int x, int y, int z)
+{
+    const orc_params *p = &bp->base;
+    int *w = (p->q != 9) ? &z : &y;
+    const int n = (p->q != 9) ? p->nz : p->ny;
+    const int m = ((*w % (2 * n)) + 2 * n) % (2 * n);
+    *w = (m < n) ? m : 2 * n - 1 - m;
+    return sidx(p, x, y, z);
+}
+
+/* Body force of the forcing scheme between walls (the reading of the walls
+ * above carried to the force): phi continued beyond a wall as its mirror
+ * image, the gradient taken with the gradient stencil at every site the
+ * force stencil reaches (ghost planes beyond a wall included),
+ * T_ab = kappa d_a phi d_b phi - delta_ab kappa |d phi|^2 / 2 there, and
+ * g_a = -sum_b (force stencil along b applied to T_ab). */
+static void bin_body_force_walls(const orc_bin_params *bp, const tables *t, const double *phi,
+                                 double *g)
+{
+    const orc_params *p = &bp->base;
+    long n = nsites(p);
+    const int dim = t->dim;
+    const double(*gs[3])[3][3] = {t->gx, t->gy, t->gz};
+    const double(*fs[3])[3][3] = {t->fx, t->fy, t->fz};
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int z = 0; z < p->nz; z++)
+        for (int y = 0; y < p->ny; y++)
+            for (int x = 0; x < p->nx; x++) {
+                double acc[3] = {0.0, 0.0, 0.0};
+                for (int sl = 0; sl < 3; sl++)
+                    for (int r = 0; r < 3; r++)
+                        for (int c = 0; c < 3; c++) {
+                            int used = 0;
+                            for (int be = 0; be < dim; be++) used |= fs[be][sl][r][c] != 0.0;
+                            if (!used) continue;
+                            const int nx_ = x + c - 1, ny_ = y + 1 - r, nz_ = z + 1 - sl;
+                            double d[3] = {0.0, 0.0, 0.0};
+                            for (int a = 0; a < dim; a++)
+                                for (int sl2 = 0; sl2 < 3; sl2++)
+                                    for (int r2 = 0; r2 < 3; r2++)
+                                        for (int c2 = 0; c2 < 3; c2++) {
+                                            const double k = gs[a][sl2][r2][c2];
+                                            if (k == 0.0) continue;
+                                            d[a] += k * phi[bin_ridx(bp, nx_ + c2 - 1, ny_ + 1 - r2,
+                                                                     nz_ + 1 - sl2)];
+                                        }
+                            double tr = 0.0;
+                            for (int a = 0; a < dim; a++) tr += p->kappa * d[a] * d[a];
+                            for (int al = 0; al < dim; al++)
+                                for (int be = 0; be < dim; be++) {
+                                    const double k = fs[be][sl][r][c];
+                                    if (k == 0.0) continue;
+                                    acc[al] -= k * (p->kappa * d[al] * d[be] - (al == be ? 0.5 * tr : 0.0));
+                                }
+                        }
+                const long s = sidx(p, x, y, z);
+                for (int a = 0; a < 3; a++) g[a * n + s] = acc[a];
+            }
+}
+
 static int opposite(const tables *t, int i)
 {
     for (int j = 0; j < t->q; j++)
@@ -944,7 +1007,6 @@ static int bin_valid(const orc_bin_params *bp)
     if (!(p->q == 9 || p->q == 19 || p->q == 15)) return 0;
     if (p->q == 9 && p->nz != 1) return 0;
     if (p->scheme != 0 && p->scheme != 1) return 0;
-    if (p->scheme == 1 && bp->wall) return 0;
     if (p->q == 15 && p->scheme != 0) return 0; /* D3Q15: tuned equilibrium only */
     return p->nx > 0 && p->ny > 0 && p->nz > 0;
 }
@@ -1017,7 +1079,8 @@ int orc_bin_run(const orc_bin_params *bp, double *f, double *g, int nsteps)
         moments(p, &t, fc, rho, j);
         order_parameter(p, &t, gc, phi);
         bin_derivatives(bp, &t, phi, grad, lap);
-        if (force) body_force(p, &t, grad, gbody); /* periodic: no walls here */
+        if (force && bp->wall) bin_body_force_walls(bp, &t, phi, gbody);
+        else if (force) body_force(p, &t, grad, gbody);
 #pragma omp parallel for collapse(2) schedule(static)
         for (int z = 0; z < p->nz; z++)
             for (int y = 0; y < p->ny; y++)
@@ -1075,7 +1138,8 @@ int orc_bin_observe(const orc_bin_params *bp, const double *f, const double *g, 
     order_parameter(p, &t, g, ph);
     bin_derivatives(bp, &t, ph, grad, lap);
     double *gbody = (double *)calloc(3 * n, sizeof(double));
-    if (p->scheme == 1) body_force(p, &t, grad, gbody);
+    if (p->scheme == 1 && bp->wall) bin_body_force_walls(bp, &t, ph, gbody);
+    else if (p->scheme == 1) body_force(p, &t, grad, gbody);
     for (long s = 0; s < n; s++) {
         if (rho) rho[s] = r[s];
         if (phi) phi[s] = ph[s];
