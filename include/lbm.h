@@ -416,15 +416,18 @@ typedef struct {
      * population streaming into a wall returns to its site reversed
      * (halfway bounce-back, no slip) and the stencils mirror phi about the
      * wall (zero normal derivative, a neutral wall).  The paper defines no
-     * walls; the forcing section only notes they are harder with forcing. */
+     * walls; the forcing section only notes they are harder with forcing.
+     * In the forcing scheme the force stencil reaches one plane further:
+     * beyond a wall it reads the gradient of the mirrored phi (its normal
+     * component reversed). */
     int wall;
     /* LBM_SCHEME_EQ (the tuned equilibrium above) or LBM_SCHEME_FORCE: the
      * forcing scheme of section "Using a forcing method" carried over, i.e.
      * an f equilibrium without the w^ab terms and a body force
      * g = -div(kappa d phi d phi - delta kappa |d phi|^2 / 2) with the force
      * stencil (F_i as in the liquid-gas API), phi advected by and the
-     * reported velocity equal to v = u + g / (2 rho).  Periodic only: the
-     * forcing scheme with wall = 1 is LBM_E_INVAL. */
+     * reported velocity equal to v = u + g / (2 rho); with walls or
+     * periodic.  Not on LBM_D3Q15 (LBM_E_INVAL). */
     int scheme;
     /* Stencil and weight overrides as in lbm_params (NaN = the paper's
      * optimum): B, D the gradient and Laplacian off-axis coefficients;

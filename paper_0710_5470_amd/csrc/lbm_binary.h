@@ -35,7 +35,9 @@
 // is the one that left r towards the wall, reversed (halfway bounce-back):
 // in the pull layout it is read from S[opp(i)][r], an entry no other site
 // reads.  The stencils read a plane beyond a wall as its mirror image in the
-// fluid (zero normal derivative of phi: a neutral wall).
+// fluid (zero normal derivative of phi: a neutral wall); in the forcing
+// scheme the force stencil reads, beyond a wall, the gradient of that
+// mirrored field.
 //
 // March.  A workgroup owns an in-plane tile of TX x TY sites (TY = 1 for
 // D2Q9, whose "planes" are rows) and a chunk of consecutive planes.  Per
@@ -384,8 +386,7 @@ __global__ __launch_bounds__(TX * TY) void bin_step_kernel(BinArgs a)
     }
 }
 
-// Forcing scheme, fused: one march per step after the phi kernel (periodic
-// lattices).  Per plane: (1) the phi field of the plane two ahead, with a
+// Forcing scheme, fused: one march per step after the phi kernel.  Per plane: (1) the phi field of the plane two ahead, with a
 // two-site in-plane halo, into an LDS ring of five planes; barrier; (2) the
 // gradient of phi on the plane ahead, with a one-site halo, into a ring of
 // three planes; barrier; (3) the collision of the current plane: phi and
@@ -395,8 +396,12 @@ __global__ __launch_bounds__(TX * TY) void bin_step_kernel(BinArgs a)
 // plane is written into the phi ring only after every thread has left the
 // collision that last read that slot (five slots, written before the first
 // barrier), and into the gradient ring only after the first barrier of the
-// next plane (three slots).
-template <class L, int TX, int TY>
+// next plane (three slots).  With walls the phi field is continued beyond a
+// wall as its mirror image (to any depth: period 2n along the marching
+// axis), so the gradient ring's planes beyond a wall are the mirrored
+// field's gradients and the force stencil reads them there; populations
+// whose source lies beyond a wall are bounced back.
+template <class L, int TX, int TY, bool WALL>
 __global__ __launch_bounds__(TX * TY) void bin_force_step_kernel(BinArgs a)
 {
     constexpr int Q = L::Q, NT = TX * TY;
@@ -438,7 +443,9 @@ __global__ __launch_bounds__(TX * TY) void bin_force_step_kernel(BinArgs a)
         off2[k] = e < PL2 ? wy * a.nx + wx : -1;
     }
     auto load_phi = [&](int p, int s) {
-        const long long base = (long long)wrapg(p, a.np) * nxy;
+        int pr = wrapg(p, WALL ? 2 * a.np : a.np);
+        if (WALL && pr >= a.np) pr = 2 * a.np - 1 - pr;
+        const long long base = (long long)pr * nxy;
 #pragma unroll
         for (int k = 0; k < N2; k++)
             if (off2[k] >= 0) phis[s][tid + k * NT] = a.phi[base + off2[k]];
@@ -502,7 +509,17 @@ __global__ __launch_bounds__(TX * TY) void bin_force_step_kernel(BinArgs a)
         }
         int P[3];
         wrap3(p, a.np, P);
+        // source of direction i; beyond a wall the own site's opposite
+        // direction (chosen on 32-bit values, one address formed)
         auto src = [&](int i) {
+            if (WALL && op<L>(i) != 0) {
+                const bool bb = op<L>(i) > 0 ? P[0] == 0 : P[0] == a.np - 1;
+                const int dir = bb ? opp<L>(i) : i;
+                const int xs = bb ? ox3[0] : from3(ox3, ox<L>(i));
+                const int ys = bb ? oy3[0] : from3(oy3, oy<L>(i));
+                const int ps = bb ? P[0] : from3(P, op<L>(i));
+                return (long long)dir * a.stride + (long long)ps * nxy + (long long)ys * a.nx + xs;
+            }
             return (long long)i * a.stride + (long long)from3(P, op<L>(i)) * nxy +
                    (long long)from3(oy3, oy<L>(i)) * a.nx + from3(ox3, ox<L>(i));
         };
@@ -645,8 +662,9 @@ __global__ void bin_moments_kernel(Geom g, bool wall, const double *__restrict__
 }
 
 // Forcing scheme: the order parameter phi = sum_i g_i of the arriving
-// populations (periodic lattices), before each step and for observables ...
-template <class L>
+// populations (bounced back at walls), before each step and for
+// observables ...
+template <class L, bool WALL>
 __global__ void bin_phi_kernel(Geom g, const double *__restrict__ gsrc, double *__restrict__ phi)
 {
     const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -655,14 +673,14 @@ __global__ void bin_phi_kernel(Geom g, const double *__restrict__ gsrc, double *
     site_coords<L>(g, s, x, y, p);
     double v = 0.0;
 #pragma unroll
-    for (int i = 0; i < L::Q; i++) v += gsrc[(long long)i * g.stride + neighbour<L>(g, x, y, p, i, -1)];
+    for (int i = 0; i < L::Q; i++) v += gsrc[bin_arrival<L>(g, WALL, x, y, p, i)];
     phi[s] = v;
 }
 
 // ... and, for observables (the velocity v = u + g / (2 rho)), the gradient
-// d phi with the gradient stencil, dphi[3][n] ...
+// d phi with the gradient stencil (walls mirrored), dphi[3][n] ...
 template <class L>
-__global__ void bin_gradient_kernel(Geom g, BinCoefs c, const double *__restrict__ phi,
+__global__ void bin_gradient_kernel(Geom g, BinCoefs c, bool wall, const double *__restrict__ phi,
                                     double *__restrict__ dphi)
 {
     const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -672,7 +690,7 @@ __global__ void bin_gradient_kernel(Geom g, BinCoefs c, const double *__restrict
     double d[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int i = 1; i < L::Q; i++) {
-        const double v = bin_grad_coef<L>(c, i) * phi[neighbour<L>(g, x, y, p, i, +1)];
+        const double v = bin_grad_coef<L>(c, i) * phi[bin_stencil_site<L>(g, wall, x, y, p, i)];
         if (L::ex[i]) d[0] += L::ex[i] * v;
         if (L::ey[i]) d[1] += L::ey[i] * v;
         if (L::ez[i]) d[2] += L::ez[i] * v;
@@ -685,9 +703,10 @@ __global__ void bin_gradient_kernel(Geom g, BinCoefs c, const double *__restrict
 // ... and the body force g_a = -sum_b d_b T_ab with the force stencil
 // (section "Using a forcing method"), T_ab = kappa d_a phi d_b phi -
 // delta_ab kappa |d phi|^2 / 2 formed at each neighbour from its gradient,
-// force[3][n].
+// force[3][n].  Beyond a wall the gradient is that of the mirror image: the
+// mirror site's, its normal component reversed.
 template <class L>
-__global__ void bin_divergence_kernel(Geom g, BinCoefs c, const double *__restrict__ dphi,
+__global__ void bin_divergence_kernel(Geom g, BinCoefs c, bool wall, const double *__restrict__ dphi,
                                       double *__restrict__ force)
 {
     const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -697,8 +716,9 @@ __global__ void bin_divergence_kernel(Geom g, BinCoefs c, const double *__restri
     double f[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int i = 1; i < L::Q; i++) {
-        const long long nb = neighbour<L>(g, x, y, p, i, +1);
+        const long long nb = bin_stencil_site<L>(g, wall, x, y, p, i);
         double d[3] = {dphi[nb], dphi[g.stride + nb], L::DIM == 3 ? dphi[2 * g.stride + nb] : 0.0};
+        if (wall && op<L>(i) != 0 && (p + op<L>(i) < 0 || p + op<L>(i) >= g.np)) d[L::DIM - 1] = -d[L::DIM - 1];
         const double h = 0.5 * c.kappa * (d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
         const double k = nnz<L>(i) == 1 ? c.Ef : c.Ff;
 #pragma unroll

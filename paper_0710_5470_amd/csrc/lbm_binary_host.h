@@ -55,7 +55,6 @@ bool bin_valid(const lbm_bin_params *p)
     if (p->tile >= bin_tile_count(p->lattice)) return false;
     if (p->wall != 0 && p->wall != 1) return false;
     if (p->scheme != LBM_SCHEME_EQ && p->scheme != LBM_SCHEME_FORCE) return false;
-    if (p->scheme == LBM_SCHEME_FORCE && p->wall) return false;  // forcing: periodic only
     if (p->lattice == LBM_D3Q19 &&
         (!std::isnan(p->wp_diag) || !std::isnan(p->wt_diag) || !std::isnan(p->wxx_diag)))
         return false;
@@ -172,7 +171,10 @@ template <class L, int TX, int TY> void bin_launch_t(lbm_bin_ctx *c, const BinAr
 {
     if constexpr (L::Q != 15)  // no forcing scheme on D3Q15
         if (c->p.scheme == LBM_SCHEME_FORCE) {
-            bin_force_step_kernel<L, TX, TY><<<nblk, TX * TY, 0, c->stream>>>(a);
+            if (c->p.wall)
+                bin_force_step_kernel<L, TX, TY, true><<<nblk, TX * TY, 0, c->stream>>>(a);
+            else
+                bin_force_step_kernel<L, TX, TY, false><<<nblk, TX * TY, 0, c->stream>>>(a);
             return;
         }
     if (c->p.wall)
@@ -192,9 +194,11 @@ const double *bin_body_force(lbm_bin_ctx *c)
     bin_dispatch(c->p.lattice, [&](auto l) {
         using L = decltype(l);
         if constexpr (L::Q != 15) {
-            bin_phi_kernel<L><<<grid1(c->n), 256, 0, c->stream>>>(g, bin_g(c, c->cur), phi);
-            bin_gradient_kernel<L><<<grid1(c->n), 256, 0, c->stream>>>(g, c->c, phi, T);
-            bin_divergence_kernel<L><<<grid1(c->n), 256, 0, c->stream>>>(g, c->c, T, force);
+            const bool w = c->p.wall != 0;
+            if (w) bin_phi_kernel<L, true><<<grid1(c->n), 256, 0, c->stream>>>(g, bin_g(c, c->cur), phi);
+            else bin_phi_kernel<L, false><<<grid1(c->n), 256, 0, c->stream>>>(g, bin_g(c, c->cur), phi);
+            bin_gradient_kernel<L><<<grid1(c->n), 256, 0, c->stream>>>(g, c->c, w, phi, T);
+            bin_divergence_kernel<L><<<grid1(c->n), 256, 0, c->stream>>>(g, c->c, w, T, force);
         }
     });
     return force;
@@ -220,8 +224,12 @@ void bin_launch_step(lbm_bin_ctx *c)
         double *phi = bws(c, c->o_phi);
         bin_dispatch(c->p.lattice, [&](auto l) {
             using L = decltype(l);
-            if constexpr (L::Q != 15)
-                bin_phi_kernel<L><<<grid1(c->n), 256, 0, c->stream>>>(bin_geom(c), bin_g(c, c->cur), phi);
+            if constexpr (L::Q != 15) {
+                if (c->p.wall)
+                    bin_phi_kernel<L, true><<<grid1(c->n), 256, 0, c->stream>>>(bin_geom(c), bin_g(c, c->cur), phi);
+                else
+                    bin_phi_kernel<L, false><<<grid1(c->n), 256, 0, c->stream>>>(bin_geom(c), bin_g(c, c->cur), phi);
+            }
         });
         a.phi = phi;
     }

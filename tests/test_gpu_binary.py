@@ -89,6 +89,12 @@ CASES = [
     (9, (5, 3), 20, dict(scheme=1)), (19, (24, 20, 18), 40, dict(scheme=1)),
     (19, (37, 11, 9), 30, dict(scheme=1, tau=0.7, tau_phi=1.2, gamma=0.8)),
     (19, (13, 9, 2), 20, dict(scheme=1)), (19, (16, 12, 1), 20, dict(scheme=1)),
+    # the forcing scheme between walls (the force stencil reaches the
+    # gradient of the mirrored phi beyond a wall): down to one plane
+    (9, (37, 29), 60, dict(scheme=1, wall=1)), (9, (33, 2), 30, dict(scheme=1, wall=1, tau=0.8)),
+    (19, (24, 20, 18), 40, dict(scheme=1, wall=1)),
+    (19, (37, 11, 9), 30, dict(scheme=1, wall=1, tau=0.7, tau_phi=1.2, gamma=0.8)),
+    (19, (13, 9, 2), 20, dict(scheme=1, wall=1)), (19, (16, 12, 1), 20, dict(scheme=1, wall=1)),
     # D3Q15 (the lattice comparison): the stable choice of the free corner
     # weights, and a short run with the isotropic defaults
     (15, (24, 20, 18), 40, Q15), (15, (37, 11, 9), 30, dict(Q15, tau=0.8, tau_phi=1.2)),
@@ -129,6 +135,7 @@ def test_binary_matches_oracle(q, shape, nsteps, kw):
 @pytest.mark.parametrize("q,shape,wall,scheme", [(9, (200, 37), 0, 0), (19, (70, 21, 13), 0, 0),
                                                  (9, (130, 21), 1, 0), (19, (70, 21, 13), 1, 0),
                                                  (9, (130, 21), 0, 1), (19, (70, 21, 13), 0, 1),
+                                                 (9, (130, 21), 1, 1), (19, (70, 21, 13), 1, 1),
                                                  (15, (70, 21, 13), 0, 0)])
 def test_binary_launch_shapes_agree_bitwise(q, shape, wall, scheme):
     lbm = _lbm()
@@ -171,7 +178,7 @@ def test_binary_rejects_bad_input():
     gp, _ = _pair(9, (16, 16))
     for bad in (dict(tau=0.5), dict(tau_phi=0.4), dict(phi_b=-1.0), dict(kappa=-0.1),
                 dict(gamma=float("nan")), dict(tile=5), dict(wall=2), dict(scheme=2),
-                dict(scheme=1, wall=1), dict(nz=2)):
+                dict(nz=2)):
         p = lbm.bin_params(lattice=9, shape=(16, 16), **bad) if "nz" not in bad else \
             lbm.bin_params(lattice=9, shape=(16, 16, 2))
         assert lbm.lbm_bin_workspace_bytes(p) == 0, bad
@@ -335,6 +342,43 @@ def test_walls_shear_mode_and_conservation_on_the_gpu(q, shape):
     n = rows * nz
     assert abs(m1 - m0) < 1e-13 * n and abs(p1 - p0) < 1e-13 * n
     sim.close()
+
+
+@pytest.mark.parametrize("scheme", [0, 1])
+@pytest.mark.parametrize("q,wshape", [(9, (256, 200)), (19, (64, 32, 48))])
+def test_walls_one_dimensional_state_equals_the_mirrored_periodic_lattice(q, wshape, scheme):
+    """A state varying only along the wall normal, moving only along it:
+    halfway bounce-back then equals mirror reflection, so the lattice
+    between walls evolves as the periodic lattice of twice the depth holding
+    the state and its mirror image (normal velocity reversed).  Checks the
+    wall marches (bounce-back, mirrored phi ring, in the forcing scheme the
+    gradient of the mirrored field beyond a wall) against the periodic
+    marches at sizes beyond the oracle's, after 300 steps."""
+    lbm = _lbm()
+    n = wshape[-1]
+    rows = int(np.prod(wshape[:-1]))
+    comp = len(wshape) - 1
+    pshape = wshape[:-1] + (2 * n,)
+    z = np.arange(n)
+    phi = np.tanh((z - n / 3) / 2.0)
+    rho = 1 + 0.03 * np.cos(0.37 * z + 0.4)
+    un = 0.01 * np.sin(0.21 * z + 0.2)
+    mirror = lambda a, sign=1: np.concatenate([a, sign * a[::-1]])
+    out = []
+    for shape, wall, prof in ((wshape, 1, lambda a, sign=1: a), (pshape, 0, mirror)):
+        gp, _ = _pair(q, shape, tau=0.8, tau_phi=1.2, gamma=0.9, wall=wall, scheme=scheme)
+        m = int(np.prod(shape))
+        u0 = np.zeros((3, m))
+        u0[comp] = np.repeat(prof(un, -1), rows)
+        _say("1d mirror q", q, "shape", shape, "wall", wall, "scheme", scheme)
+        sim = lbm.BinarySimulation(gp, np.repeat(prof(rho), rows), np.repeat(prof(phi), rows), u0)
+        sim.step(300)
+        out.append([t[..., :rows * n].clone() for t in sim.moments()])
+        sim.close()
+    errs = [float((a - b).abs().max()) for a, b in zip(*out)]
+    _say("max diff rho, phi, v, mu", errs)
+    assert max(errs) < 1e-13
+    assert float(out[0][2][comp].abs().max()) > 1e-4   # the flow is not trivial
 
 
 @pytest.mark.parametrize("q,n,radius", [(9, 64, 16.0), (19, 48, 12.0)])
