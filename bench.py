@@ -44,10 +44,12 @@ WORKLOADS = {
 # binary fluid (FP64 f and g): name: (lattice, shape); phi_a = -0.02,
 # phi_b = 0.02, kappa = 0.04, gamma = 1, tau = tau_phi = 1; a drop of
 # phi = +1 (radius side/4, tanh width 2) in phi = -1, rho = 1 + noise 0.01
-BIN_WORKLOADS = {  # name: (lattice, shape, scheme)
-    "d3q19_256_fp64_binary": (19, (256, 256, 256), 0),
-    "d2q9_1024_fp64_binary": (9, (1024, 1024), 0),
-    "d3q19_256_fp64_binary_force": (19, (256, 256, 256), 1),
+BIN_WORKLOADS = {  # name: (lattice, shape, scheme, walls at both ends of the last axis)
+    "d3q19_256_fp64_binary": (19, (256, 256, 256), 0, 0),
+    "d2q9_1024_fp64_binary": (9, (1024, 1024), 0, 0),
+    "d3q19_256_fp64_binary_force": (19, (256, 256, 256), 1, 0),
+    "d3q19_256_fp64_binary_walls": (19, (256, 256, 256), 0, 1),
+    "d3q19_256_fp64_binary_force_walls": (19, (256, 256, 256), 1, 1),
 }
 BIN_PARAMS = dict(phi_a=-0.02, phi_b=0.02, kappa=0.04, gamma=1.0, tau=1.0, tau_phi=1.0)
 BIN_KERNEL_SOURCES = ["paper_0710_5470_amd/csrc/lbm_binary.h", "paper_0710_5470_amd/csrc/lbm_lattice.h",
@@ -185,26 +187,29 @@ def cpu_baseline(wl):
 def make_binary(wl):
     """lbm_bin_params and the initial (rho, phi) of a binary workload."""
     from paper_0710_5470_amd import inputs, lbm
-    q, shape, scheme = BIN_WORKLOADS[wl]
+    q, shape, scheme, wall = BIN_WORKLOADS[wl]
     phi = inputs.tanh_drop(shape, shape[0] / 4.0, 1.0, -1.0, 2.0)
     rho = 1.0 + inputs.uniform_noise(shape, 0.01, 41)
-    return lbm.bin_params(lattice=q, shape=shape, scheme=scheme, **BIN_PARAMS), rho, phi
+    return lbm.bin_params(lattice=q, shape=shape, scheme=scheme, wall=wall, **BIN_PARAMS), rho, phi
 
 
 def cpu_baseline_binary(wl):
     """The FP64 CPU oracle's binary stepper on a bounded sample of the same
-    workload: a 256 x 256 x 24 slab (D3Q19, 36 steps) or the 1024 x 1024 box
-    (D2Q9, 100 steps), about 10 s on 8 cores."""
+    workload: a 256 x 256 x 24 slab (D3Q19, 36 steps; 8 for the forcing
+    scheme between walls) or the 1024 x 1024 box (D2Q9, 100 steps), about
+    10 s on 8 cores."""
     import numpy as np
     import oracle
     from paper_0710_5470_amd import inputs
-    q, shape, scheme = BIN_WORKLOADS[wl]
+    q, shape, scheme, wall = BIN_WORKLOADS[wl]
     sample = (256, 256, 24) if q == 19 else (1024, 1024)
     phi = inputs.tanh_drop(sample, min(sample) / 3.0, 1.0, -1.0, 2.0)
     rho = 1.0 + inputs.uniform_noise(sample, 0.01, 41)
-    bp = oracle.bin_params(q=q, shape=sample, scheme=scheme, **BIN_PARAMS)
+    bp = oracle.bin_params(q=q, shape=sample, scheme=scheme, wall=wall, **BIN_PARAMS)
     f, g = oracle.bin_init(bp, rho, phi)
     steps = 36 if q == 19 else 100
+    if scheme and wall:
+        steps = 8  # the oracle's walled force recomputes the gradient per stencil neighbour
     cores = oracle.max_threads()
     t0 = time.perf_counter()
     f, g = oracle.bin_run(bp, f, g, steps)
@@ -216,8 +221,8 @@ def cpu_baseline_binary(wl):
     dt1 = time.perf_counter() - t1
     oracle.set_threads(cores)
     return {"value": sites * steps / dt / 1e6, "unit": "MLUPS", "cores": cores, "kind": "oracle",
-            "sample": "%s periodic lattice, same physics, %d steps, FP64 C oracle (%.2f s)"
-                      % ("x".join(map(str, sample)), steps, dt),
+            "sample": "%s %s lattice, same physics, %d steps, FP64 C oracle (%.2f s)"
+                      % ("x".join(map(str, sample)), "walled" if wall else "periodic", steps, dt),
             "cpu_model": cpu_model(), "single_thread_mlups": sites / dt1 / 1e6}
 
 
@@ -226,7 +231,7 @@ def bench_binary(args):
     import torch
     from paper_0710_5470_amd import autotune, lbm
     wl = args.workload
-    q, shape, scheme = BIN_WORKLOADS[wl]
+    q, shape, scheme, wall = BIN_WORKLOADS[wl]
     p, rho, phi = make_binary(wl)
     sim = lbm.BinarySimulation(p, rho, phi)
     n = sim.n
@@ -272,6 +277,7 @@ def bench_binary(args):
         "data": "synthetic",
         "config": {"workload": wl, "lattice": "D3Q19" if q == 19 else "D2Q9", "extent": list(shape),
                    "model": "binary fluid", "scheme": "force" if scheme else "equilibrium",
+                   "boundaries": "walls at z = -1/2 and n - 1/2" if wall else "periodic",
                    **BIN_PARAMS,
                    "init": "phi drop R=%g (tanh width 2) + rho noise 0.01 (seed 41)" % (shape[0] / 4.0),
                    "launch": {"tile": lbm.lbm_bin_tile_shape(q, tile), "planes_per_workgroup": planes,
