@@ -162,7 +162,7 @@ def autotune_binary(sim, steps=10, reps=2, verbose=False):
     """Time every launch shape of a BinarySimulation (its state advances by
     the timing steps) and apply the fastest.  Returns (tile, planes, ms)."""
     p = sim.p
-    np_ = p.nz if p.lattice == lbm.D3Q19 else p.ny
+    np_ = p.ny if p.lattice == lbm.D2Q9 else p.nz
     stream = torch.cuda.current_stream()
     results = []
     for t, c in binary_candidates(p.lattice, np_):
