@@ -347,8 +347,9 @@ def test_walls_shear_mode_and_conservation_on_the_gpu(q, shape):
     sim.close()
 
 
-@pytest.mark.parametrize("scheme", [0, 1])
-@pytest.mark.parametrize("q,wshape", [(9, (256, 200)), (19, (64, 32, 48))])
+@pytest.mark.parametrize("q,wshape,scheme", [(9, (256, 200), 0), (9, (256, 200), 1),
+                                             (19, (64, 32, 48), 0), (19, (64, 32, 48), 1),
+                                             (15, (64, 32, 48), 0)])
 def test_walls_one_dimensional_state_equals_the_mirrored_periodic_lattice(q, wshape, scheme):
     """A state varying only along the wall normal, moving only along it:
     halfway bounce-back then equals mirror reflection, so the lattice
@@ -369,7 +370,8 @@ def test_walls_one_dimensional_state_equals_the_mirrored_periodic_lattice(q, wsh
     mirror = lambda a, sign=1: np.concatenate([a, sign * a[::-1]])
     out = []
     for shape, wall, prof in ((wshape, 1, lambda a, sign=1: a), (pshape, 0, mirror)):
-        gp, _ = _pair(q, shape, tau=0.8, tau_phi=1.2, gamma=0.9, wall=wall, scheme=scheme)
+        gp, _ = _pair(q, shape, tau=0.8, tau_phi=1.2, gamma=0.9, wall=wall, scheme=scheme,
+                      **(Q15 if q == 15 else {}))
         m = int(np.prod(shape))
         u0 = np.zeros((3, m))
         u0[comp] = np.repeat(prof(un, -1), rows)
