@@ -378,7 +378,7 @@ int lbm_warm_project(int nprob, int side, int cpad, const float *dev_pred, const
  * phi_a phi^2/2 + phi_b phi^4/4 plus kappa |grad phi|^2/2 (phi_a < 0 gives
  * two phases phi = +-sqrt(-phi_a/phi_b) with a tanh interface of width
  * sqrt(-2 kappa/phi_a)).  Two FP64 distributions advance together on a
- * periodic D2Q9 or D3Q19 lattice:
+ * D2Q9, D3Q19 or D3Q15 lattice, periodic or between two walls (wall):
  *   - f_i relaxes (time tau) to the tuned equilibrium of Eq. (equilibrium)/
  *     (feq0) with phi in the place of the differentiated density: bulk
  *     pressure rho/3 + phi_a phi^2/2 + 3 phi_b phi^4/4 on the w^p weights,

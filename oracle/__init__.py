@@ -223,7 +223,7 @@ def bin_params(q=9, shape=(64, 64), phi_a=-0.02, phi_b=0.02, kappa=0.04, tau=1.0
     """Symmetric binary fluid: bulk free energy phi_a phi^2/2 + phi_b phi^4/4
     plus kappa |grad phi|^2 / 2, ideal-gas carrier rho/3.  wall = 1 bounds
     the last axis (z in 3D, y in 2D) by two halfway bounce-back walls;
-    scheme = 1 is the forcing scheme (periodic only)."""
+    scheme = 1 is the forcing scheme (with or without walls; not on D3Q15)."""
     base = params(q=q, scheme=scheme, shape=shape, a=0.0, b=0.0, T=0.0, kappa=kappa, tau=tau,
                   lambda_on=0, **over)
     return OrcBinParams(base, phi_a, phi_b, gamma, tau_phi, int(wall))

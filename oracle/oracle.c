@@ -20,7 +20,8 @@
  *
  * State representation: f[i][z][y][x] holds f_i(r,t), the population at
  * site r after streaming (the paper's f_i(r,t)).  All arrays are SoA with x
- * fastest.  Every boundary is periodic.  Units: dx = dt = c = 1.
+ * fastest.  Every boundary is periodic, except the binary stepper's optional
+ * walls (below).  Units: dx = dt = c = 1.
  *
  * Readings of the paper taken here (each is listed with its justification in
  * the design notes of the repository):
