@@ -237,7 +237,8 @@ def test_optimum_stencils_suppress_binary_spurious_velocities(q, n, radius):
 
 
 FULL = [("d3q19_256_fp64_binary", 19, (256, 256, 256), 0), ("d2q9_1024_fp64_binary", 9, (1024, 1024), 0),
-        ("d3q19_256_fp64_binary_force", 19, (256, 256, 256), 1)]
+        ("d3q19_256_fp64_binary_force", 19, (256, 256, 256), 1),
+        ("D3Q15 256^3 (the lattice comparison, stable corner weights)", 15, (256, 256, 256), 0)]
 
 
 @pytest.mark.parametrize("name,q,shape,scheme", FULL)
@@ -249,7 +250,7 @@ def test_full_size_binary_matches_oracle_on_sampled_sites(name, q, shape, scheme
     import oracle
     from paper_0710_5470_amd import autotune, inputs
     lbm = _lbm()
-    gp, op = _pair(q, shape, scheme=scheme)
+    gp, op = _pair(q, shape, scheme=scheme, **(Q15 if q == 15 else {}))
     n = int(np.prod(shape))
     R = shape[0] / 4.0
     phi = inputs.tanh_drop(shape, R, 1.0, -1.0, 2.0).reshape(-1)
@@ -262,7 +263,7 @@ def test_full_size_binary_matches_oracle_on_sampled_sites(name, q, shape, scheme
     sim.step(1)
     f1, g1 = [t.cpu().numpy() for t in sim.get_state()]
     rng = np.random.default_rng(5)
-    nz = shape[2] if q == 19 else 1
+    nz = shape[2] if len(shape) == 3 else 1
     xyz = np.stack([rng.integers(0, shape[0], 512), rng.integers(0, shape[1], 512),
                     rng.integers(0, nz, 512)], 1)
     # include the lattice's corners (wrap-around in every direction)

@@ -35,25 +35,27 @@ def _dpsi(phi):
 
 def _textbook_weight(e):
     """Isothermal equilibrium weights by speed: D2Q9 4/9, 1/9, 1/36;
-    D3Q19 1/3, 1/18, 1/36."""
+    D3Q19 1/3, 1/18, 1/36; D3Q15 2/9, 1/9, 1/72."""
     q = len(e)
     e2 = (e ** 2).sum(1)
     if q == 9:
         return np.where(e2 == 0, 4 / 9, np.where(e2 == 1, 1 / 9, 1 / 36))
+    if q == 15:
+        return np.where(e2 == 0, 2 / 9, np.where(e2 == 1, 1 / 9, 1 / 72))
     return np.where(e2 == 0, 1 / 3, np.where(e2 == 1, 1 / 18, 1 / 36))
 
 
-@pytest.mark.parametrize("scheme", [0, 1])
-@pytest.mark.parametrize("q", [9, 19])
-def test_binary_feq_moments_are_the_free_energy_pressure_tensor(q, scheme):
+@pytest.mark.parametrize("q,scheme,over", [(9, 0, {}), (9, 1, {}), (19, 0, {}), (19, 1, {}), (15, 0, {}),
+                                           (15, 0, dict(wt_d=1 / 8, wp_d=1 / 8, wxx_d=-1 / 32, B=1 / 12))])
+def test_binary_feq_moments_are_the_free_energy_pressure_tensor(q, scheme, over):
     """Equilibrium scheme: the whole pressure tensor of the free energy.
     Forcing scheme: its isotropic part (p0 - kappa phi lap phi) delta; the
     rest, kappa d phi d phi - kappa |d phi|^2 delta / 2, is the stress whose
     divergence the body force supplies."""
-    bp = O.bin_params(q=q, shape=(4, 4, 4) if q == 19 else (4, 4), phi_a=PA, phi_b=PB,
-                      kappa=KAPPA, scheme=scheme)
+    bp = O.bin_params(q=q, shape=(4, 4) if q == 9 else (4, 4, 4), phi_a=PA, phi_b=PB,
+                      kappa=KAPPA, scheme=scheme, **over)
     e = O.tables(bp.base)["e"].astype(float)
-    dim = 3 if q == 19 else 2
+    dim = 2 if q == 9 else 3
     rng = np.random.default_rng(11)
     for _ in range(20):
         rho = rng.uniform(0.8, 1.2)
@@ -78,13 +80,13 @@ def test_binary_feq_moments_are_the_free_energy_pressure_tensor(q, scheme):
         np.testing.assert_allclose(got2, want2, atol=1e-14)
 
 
-@pytest.mark.parametrize("q", [9, 19])
+@pytest.mark.parametrize("q", [9, 19, 15])
 def test_binary_geq_moments(q):
     gamma = 0.7
-    bp = O.bin_params(q=q, shape=(4, 4, 4) if q == 19 else (4, 4), phi_a=PA, phi_b=PB,
+    bp = O.bin_params(q=q, shape=(4, 4) if q == 9 else (4, 4, 4), phi_a=PA, phi_b=PB,
                       kappa=KAPPA, gamma=gamma)
     e = O.tables(bp.base)["e"].astype(float)
-    dim = 3 if q == 19 else 2
+    dim = 2 if q == 9 else 3
     rng = np.random.default_rng(12)
     for _ in range(20):
         phi = rng.uniform(-1.1, 1.1)
@@ -100,13 +102,15 @@ def test_binary_geq_moments(q):
                                    atol=1e-15)
 
 
-@pytest.mark.parametrize("q", [9, 19])
+@pytest.mark.parametrize("q", [9, 19, 15])
 def test_binary_feq_at_zero_phi_is_the_textbook_isothermal_equilibrium(q):
-    bp = O.bin_params(q=q, shape=(4, 4, 4) if q == 19 else (4, 4), phi_a=PA, phi_b=PB,
+    """At phi = 0 the tuned equilibrium with the default weights (for D3Q15
+    the isotropic ones) is the textbook isothermal equilibrium."""
+    bp = O.bin_params(q=q, shape=(4, 4) if q == 9 else (4, 4, 4), phi_a=PA, phi_b=PB,
                       kappa=KAPPA)
     e = O.tables(bp.base)["e"].astype(float)
     w = _textbook_weight(e)
-    dim = 3 if q == 19 else 2
+    dim = 2 if q == 9 else 3
     rng = np.random.default_rng(13)
     for _ in range(10):
         rho = rng.uniform(0.5, 1.5)
@@ -281,8 +285,8 @@ def test_binary_shear_wave_decays_with_viscosity(q):
     assert abs(np.log(a0 / a1) / 1000 / want - 1) < 2e-3
 
 
-@pytest.mark.parametrize("scheme", [0, 1])
-@pytest.mark.parametrize("q,shape", [(9, (13, 11)), (19, (7, 6, 5))])
+@pytest.mark.parametrize("q,shape,scheme", [(9, (13, 11), 0), (9, (13, 11), 1), (19, (7, 6, 5), 0),
+                                            (19, (7, 6, 5), 1), (15, (7, 6, 5), 0)])
 def test_site_local_collision_matches_the_stepper(q, shape, scheme):
     """The site-local evaluation (used to check large lattices at sampled
     sites) gives the stepper's post-collision values: after one step the
@@ -299,7 +303,7 @@ def test_site_local_collision_matches_the_stepper(q, shape, scheme):
     f1, g1 = O.bin_run(bp, f, g, 1)
     e = O.tables(bp.base)["e"]
     nx, ny = shape[0], shape[1]
-    nz = shape[2] if q == 19 else 1
+    nz = shape[2] if len(shape) == 3 else 1
     xyz = np.array([(x, y, z) for z in range(nz) for y in range(ny) for x in range(nx)])
     fo, go = O.bin_collide_sites(bp, f, g, xyz)
     for i in range(q):
