@@ -842,14 +842,20 @@ static int bin_beyond(const orc_bin_params *bp, int y, int z)
 /* Site index with the bounded axis reflected to any depth: the fluid is
  * continued beyond each wall as its mirror image, so along that axis the
  * continuation has period 2n. */
-static long bin_ridx(const orc_bin_params *bp, int x, int y, int z)
+static void bin_reflect(const orc_bin_params *bp, int *y, int *z)
 {
     const orc_params *p = &bp->base;
-    int *w = (p->q != 9) ? &z : &y;
+    if (!bp->wall) return;
+    int *w = (p->q != 9) ? z : y;
     const int n = (p->q != 9) ? p->nz : p->ny;
     const int m = ((*w % (2 * n)) + 2 * n) % (2 * n);
     *w = (m < n) ? m : 2 * n - 1 - m;
-    return sidx(p, x, y, z);
+}
+
+static long bin_ridx(const orc_bin_params *bp, int x, int y, int z)
+{
+    bin_reflect(bp, &y, &z);
+    return sidx(&bp->base, x, y, z);
 }
 
 /* Body force of the forcing scheme between walls (the reading of the walls
@@ -1193,7 +1199,7 @@ void orc_bin_geq_site(const orc_bin_params *bp, double phi, const double *u, dou
 int orc_bin_collide_sites(const orc_bin_params *bp, const double *f, const double *g, int nsite,
                           const int *xyz, double *fout, double *gout)
 {
-    if (!bin_valid(bp) || bp->wall) return -1; /* periodic lattices only */
+    if (!bin_valid(bp)) return -1;
     const orc_params *p = &bp->base;
     tables t;
     build_tables(p, &t);
@@ -1218,8 +1224,11 @@ int orc_bin_collide_sites(const orc_bin_params *bp, const double *f, const doubl
                     int any = kl != 0.0;
                     for (int a = 0; a < t.dim; a++) any |= gs[a][sl][r][c] != 0.0;
                     if (!any) continue;
-                    /* rho_at sums any distribution: here g, giving phi */
-                    double ph = rho_at(p, &t, g, x + c - 1, y + 1 - r, z + 1 - sl);
+                    /* rho_at sums any distribution: here g, giving phi (a site
+                     * beyond a wall: its mirror image) */
+                    int yy = y + 1 - r, zz = z + 1 - sl;
+                    bin_reflect(bp, &yy, &zz);
+                    double ph = rho_at(p, &t, g, x + c - 1, yy, zz);
                     for (int a = 0; a < t.dim; a++) d[a] += gs[a][sl][r][c] * ph;
                     lap += kl * ph;
                 }
@@ -1238,8 +1247,21 @@ int orc_bin_collide_sites(const orc_bin_params *bp, const double *f, const doubl
                         int any = 0;
                         for (int be = 0; be < t.dim; be++) any |= (fs[be][sl][r][c] != 0.0);
                         if (!any) continue;
-                        double dn[3];
-                        grad_at(p, &t, g, x + c - 1, y + 1 - r, z + 1 - sl, dn);
+                        double dn[3] = {0.0, 0.0, 0.0};
+                        if (!bp->wall) {
+                            grad_at(p, &t, g, x + c - 1, y + 1 - r, z + 1 - sl, dn);
+                        } else { /* gradient of the mirrored phi, ghost sites included */
+                            for (int a = 0; a < t.dim; a++)
+                                for (int s2 = 0; s2 < 3; s2++)
+                                    for (int r2 = 0; r2 < 3; r2++)
+                                        for (int c2 = 0; c2 < 3; c2++) {
+                                            const double k2 = gs[a][s2][r2][c2];
+                                            if (k2 == 0.0) continue;
+                                            int yy = y + 1 - r + 1 - r2, zz = z + 1 - sl + 1 - s2;
+                                            bin_reflect(bp, &yy, &zz);
+                                            dn[a] += k2 * rho_at(p, &t, g, x + c - 1 + c2 - 1, yy, zz);
+                                        }
+                        }
                         double tr = 0.0;
                         for (int g2 = 0; g2 < t.dim; g2++) tr += p->kappa * dn[g2] * dn[g2];
                         for (int al = 0; al < t.dim; al++)

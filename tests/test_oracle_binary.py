@@ -285,14 +285,16 @@ def test_binary_shear_wave_decays_with_viscosity(q):
     assert abs(np.log(a0 / a1) / 1000 / want - 1) < 2e-3
 
 
+@pytest.mark.parametrize("wall", [0, 1])
 @pytest.mark.parametrize("q,shape,scheme", [(9, (13, 11), 0), (9, (13, 11), 1), (19, (7, 6, 5), 0),
                                             (19, (7, 6, 5), 1), (15, (7, 6, 5), 0)])
-def test_site_local_collision_matches_the_stepper(q, shape, scheme):
+def test_site_local_collision_matches_the_stepper(q, shape, scheme, wall):
     """The site-local evaluation (used to check large lattices at sampled
     sites) gives the stepper's post-collision values: after one step the
-    population arriving at r + e_i is the one collided at r."""
+    population arriving at r + e_i is the one collided at r, or, where
+    r + e_i lies beyond a wall, the one arriving back at r reversed."""
     bp = O.bin_params(q=q, shape=shape, phi_a=PA, phi_b=PB, kappa=KAPPA, tau=0.8, tau_phi=1.2,
-                      gamma=0.9, scheme=scheme)
+                      gamma=0.9, scheme=scheme, wall=wall)
     rng = np.random.default_rng(15)
     n = int(np.prod(shape))
     u0 = 0.03 * rng.standard_normal((3, n))
@@ -306,11 +308,17 @@ def test_site_local_collision_matches_the_stepper(q, shape, scheme):
     nz = shape[2] if len(shape) == 3 else 1
     xyz = np.array([(x, y, z) for z in range(nz) for y in range(ny) for x in range(nx)])
     fo, go = O.bin_collide_sites(bp, f, g, xyz)
+    ax, nw = (2, nz) if len(shape) == 3 else (1, ny)
+    own = (xyz[:, 2] * ny + xyz[:, 1]) * nx + xyz[:, 0]
+    opp = [int(np.flatnonzero((e == -e[i]).all(1))[0]) for i in range(q)]
     for i in range(q):
         dst = (((xyz[:, 2] + e[i, 2]) % nz) * ny + (xyz[:, 1] + e[i, 1]) % ny) * nx \
             + (xyz[:, 0] + e[i, 0]) % nx
-        np.testing.assert_allclose(f1[i, dst], fo[:, i], rtol=0, atol=1e-15)
-        np.testing.assert_allclose(g1[i, dst], go[:, i], rtol=0, atol=1e-15)
+        beyond = wall & ((xyz[:, ax] + e[i, ax] < 0) | (xyz[:, ax] + e[i, ax] >= nw))
+        got_f = np.where(beyond, f1[opp[i], own], f1[i, dst])
+        got_g = np.where(beyond, g1[opp[i], own], g1[i, dst])
+        np.testing.assert_allclose(got_f, fo[:, i], rtol=0, atol=1e-15)
+        np.testing.assert_allclose(got_g, go[:, i], rtol=0, atol=1e-15)
 
 
 # ---- walls (halfway bounce-back, mirrored stencils) --------------------------
