@@ -236,21 +236,24 @@ def test_optimum_stencils_suppress_binary_spurious_velocities(q, n, radius):
         assert v > 3 * best, name
 
 
-FULL = [("d3q19_256_fp64_binary", 19, (256, 256, 256), 0), ("d2q9_1024_fp64_binary", 9, (1024, 1024), 0),
-        ("d3q19_256_fp64_binary_force", 19, (256, 256, 256), 1),
-        ("D3Q15 256^3 (the lattice comparison, stable corner weights)", 15, (256, 256, 256), 0)]
+FULL = [("d3q19_256_fp64_binary", 19, (256, 256, 256), 0, 0), ("d2q9_1024_fp64_binary", 9, (1024, 1024), 0, 0),
+        ("d3q19_256_fp64_binary_force", 19, (256, 256, 256), 1, 0),
+        ("d3q19_256_fp64_binary_walls", 19, (256, 256, 256), 0, 1),
+        ("d3q19_256_fp64_binary_force_walls", 19, (256, 256, 256), 1, 1),
+        ("D3Q15 256^3 (the lattice comparison, stable corner weights)", 15, (256, 256, 256), 0, 0)]
 
 
-@pytest.mark.parametrize("name,q,shape,scheme", FULL)
-def test_full_size_binary_matches_oracle_on_sampled_sites(name, q, shape, scheme):
+@pytest.mark.parametrize("name,q,shape,scheme,wall", FULL)
+def test_full_size_binary_matches_oracle_on_sampled_sites(name, q, shape, scheme, wall):
     """The benchmark's lattices in the launch the benchmark times (the
     autotuned one): after one step the populations arriving from 512
-    sampled sites equal the oracle's site-local collision there; the state
-    stays finite and conserves its totals over 50 further steps."""
+    sampled sites (or, beyond a wall, arriving back at them reversed) equal
+    the oracle's site-local collision there; the state stays finite and
+    conserves its totals over 50 further steps (momentum: periodic only)."""
     import oracle
     from paper_0710_5470_amd import autotune, inputs
     lbm = _lbm()
-    gp, op = _pair(q, shape, scheme=scheme, **(Q15 if q == 15 else {}))
+    gp, op = _pair(q, shape, scheme=scheme, wall=wall, **(Q15 if q == 15 else {}))
     n = int(np.prod(shape))
     R = shape[0] / 4.0
     phi = inputs.tanh_drop(shape, R, 1.0, -1.0, 2.0).reshape(-1)
@@ -270,18 +273,23 @@ def test_full_size_binary_matches_oracle_on_sampled_sites(name, q, shape, scheme
     xyz[:2] = [[0, 0, 0], [shape[0] - 1, shape[1] - 1, nz - 1]]
     fo, go = oracle.bin_collide_sites(op, f0, g0, xyz)
     e = oracle.tables(op.base)["e"]
+    ax, nw = (2, nz) if len(shape) == 3 else (1, shape[1])
+    own = (xyz[:, 2] * shape[1] + xyz[:, 1]) * shape[0] + xyz[:, 0]
+    opp = [int(np.flatnonzero((e == -e[i]).all(1))[0]) for i in range(q)]
     for i in range(q):
         dst = (((xyz[:, 2] + e[i, 2]) % nz) * shape[1] + (xyz[:, 1] + e[i, 1]) % shape[1]) \
             * shape[0] + (xyz[:, 0] + e[i, 0]) % shape[0]
-        assert np.abs(f1[i, dst] - fo[:, i]).max() < 1e-13
-        assert np.abs(g1[i, dst] - go[:, i]).max() < 1e-13
+        beyond = wall & ((xyz[:, ax] + e[i, ax] < 0) | (xyz[:, ax] + e[i, ax] >= nw))
+        assert np.abs(np.where(beyond, f1[opp[i], own], f1[i, dst]) - fo[:, i]).max() < 1e-13
+        assert np.abs(np.where(beyond, g1[opp[i], own], g1[i, dst]) - go[:, i]).max() < 1e-13
     del f0, g0, f1, g1
     m0, p0, j0 = sim.invariants()
     sim.step(50)
     m1, p1, j1 = sim.invariants()
     assert abs(m1 - m0) < 1e-12 * abs(m0)
     assert abs(p1 - p0) < 1e-12 * n
-    assert np.abs(np.array(j1) - np.array(j0)).max() < 1e-12 * n
+    if not wall:
+        assert np.abs(np.array(j1) - np.array(j0)).max() < 1e-12 * n
     assert np.isfinite(sim.max_spurious_u())
     sim.close()
 
