@@ -455,8 +455,8 @@ def test_drop_on_a_neutral_wall_relaxes_to_a_hemisphere(scheme):
     cap of contact angle theta), against the same ratio of the free drop
     (measured after 4000 steps: theta 89.6 deg and a ratio 0.007 from the
     free drop's in the equilibrium scheme, 89.96 deg and 0.0003 in the
-    forcing scheme; the equilibrium scheme is still relaxing near the
-    contact line, where its spurious velocity is 5x the free drop's)."""
+    forcing scheme; near the contact line the equilibrium scheme keeps a
+    spurious velocity 5x the free drop's, to 40,000 steps at least)."""
     lbm = _lbm()
     n, nz, R, steps = 48, 24, 12.0, 4000
     c = n // 2
