@@ -386,8 +386,9 @@ __global__ __launch_bounds__(TX * TY) void bin_step_kernel(BinArgs a)
     }
 }
 
-// Forcing scheme, fused: one march per step after the phi kernel.  Per plane: (1) the phi field of the plane two ahead, with a
-// two-site in-plane halo, into an LDS ring of five planes; barrier; (2) the
+// Forcing scheme, fused: one march per step after the phi kernel.  Per
+// plane: (1) the phi field of the plane two ahead, with a two-site in-plane
+// halo, into an LDS ring of five planes; barrier; (2) the
 // gradient of phi on the plane ahead, with a one-site halo, into a ring of
 // three planes; barrier; (3) the collision of the current plane: phi and
 // lap(phi) from the phi ring, the body force -sum_b d_b T_ab with the force
