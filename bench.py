@@ -50,7 +50,13 @@ BIN_WORKLOADS = {  # name: (lattice, shape, scheme, walls at both ends of the la
     "d3q19_256_fp64_binary_force": (19, (256, 256, 256), 1, 0),
     "d3q19_256_fp64_binary_walls": (19, (256, 256, 256), 0, 1),
     "d3q19_256_fp64_binary_force_walls": (19, (256, 256, 256), 1, 1),
+    "d3q15_256_fp64_binary": (15, (256, 256, 256), 0, 0),
 }
+# D3Q15 (the lattice comparison) at its stable choice of the free corner
+# weights: w^t = w^p = 1/8 and w^xx = -1/32 on the corners, B = 1/12
+BIN_OVERRIDES = {"d3q15_256_fp64_binary": dict(wt_diag=1 / 8, wp_diag=1 / 8, wxx_diag=-1 / 32, B=1 / 12)}
+_ORACLE_NAMES = {"wt_diag": "wt_d", "wp_diag": "wp_d", "wxx_diag": "wxx_d", "B": "B", "D": "D"}
+LATTICE_NAMES = {9: "D2Q9", 19: "D3Q19", 15: "D3Q15"}
 BIN_PARAMS = dict(phi_a=-0.02, phi_b=0.02, kappa=0.04, gamma=1.0, tau=1.0, tau_phi=1.0)
 BIN_KERNEL_SOURCES = ["paper_0710_5470_amd/csrc/lbm_binary.h", "paper_0710_5470_amd/csrc/lbm_lattice.h",
                       "paper_0710_5470_amd/build.py"]
@@ -190,7 +196,8 @@ def make_binary(wl):
     q, shape, scheme, wall = BIN_WORKLOADS[wl]
     phi = inputs.tanh_drop(shape, shape[0] / 4.0, 1.0, -1.0, 2.0)
     rho = 1.0 + inputs.uniform_noise(shape, 0.01, 41)
-    return lbm.bin_params(lattice=q, shape=shape, scheme=scheme, wall=wall, **BIN_PARAMS), rho, phi
+    return lbm.bin_params(lattice=q, shape=shape, scheme=scheme, wall=wall, **BIN_PARAMS,
+                          **BIN_OVERRIDES.get(wl, {})), rho, phi
 
 
 def cpu_baseline_binary(wl):
@@ -202,12 +209,13 @@ def cpu_baseline_binary(wl):
     import oracle
     from paper_0710_5470_amd import inputs
     q, shape, scheme, wall = BIN_WORKLOADS[wl]
-    sample = (256, 256, 24) if q == 19 else (1024, 1024)
+    sample = (1024, 1024) if q == 9 else (256, 256, 24)
     phi = inputs.tanh_drop(sample, min(sample) / 3.0, 1.0, -1.0, 2.0)
     rho = 1.0 + inputs.uniform_noise(sample, 0.01, 41)
-    bp = oracle.bin_params(q=q, shape=sample, scheme=scheme, wall=wall, **BIN_PARAMS)
+    over = {_ORACLE_NAMES[k]: v for k, v in BIN_OVERRIDES.get(wl, {}).items()}
+    bp = oracle.bin_params(q=q, shape=sample, scheme=scheme, wall=wall, **BIN_PARAMS, **over)
     f, g = oracle.bin_init(bp, rho, phi)
-    steps = 36 if q == 19 else 100
+    steps = 100 if q == 9 else 36
     if scheme and wall:
         steps = 8  # the oracle's walled force recomputes the gradient per stencil neighbour
     cores = oracle.max_threads()
@@ -275,10 +283,10 @@ def bench_binary(args):
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": wl, "lattice": "D3Q19" if q == 19 else "D2Q9", "extent": list(shape),
+        "config": {"workload": wl, "lattice": LATTICE_NAMES[q], "extent": list(shape),
                    "model": "binary fluid", "scheme": "force" if scheme else "equilibrium",
                    "boundaries": "walls at z = -1/2 and n - 1/2" if wall else "periodic",
-                   **BIN_PARAMS,
+                   **BIN_PARAMS, **BIN_OVERRIDES.get(wl, {}),
                    "init": "phi drop R=%g (tanh width 2) + rho noise 0.01 (seed 41)" % (shape[0] / 4.0),
                    "launch": {"tile": lbm.lbm_bin_tile_shape(q, tile), "planes_per_workgroup": planes,
                               "workgroups": wgs, "autotuned": tuned}},

@@ -240,7 +240,7 @@ FULL = [("d3q19_256_fp64_binary", 19, (256, 256, 256), 0, 0), ("d2q9_1024_fp64_b
         ("d3q19_256_fp64_binary_force", 19, (256, 256, 256), 1, 0),
         ("d3q19_256_fp64_binary_walls", 19, (256, 256, 256), 0, 1),
         ("d3q19_256_fp64_binary_force_walls", 19, (256, 256, 256), 1, 1),
-        ("D3Q15 256^3 (the lattice comparison, stable corner weights)", 15, (256, 256, 256), 0, 0)]
+        ("d3q15_256_fp64_binary", 15, (256, 256, 256), 0, 0)]
 
 
 @pytest.mark.parametrize("name,q,shape,scheme,wall", FULL)
