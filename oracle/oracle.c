@@ -38,7 +38,13 @@
  *    Eq. (pt), with the 3D gradient stencil;
  *  - the rest forcing term is F_0 = -sum_{i>=1} F_i (zeroth forcing moment);
  *  - the equilibrium and forcing use u = j / rho; the reported velocity of
- *    the forcing scheme is v = u + g / (2 rho) (end of Appendix A).
+ *    the forcing scheme is v = u + g / (2 rho) (end of Appendix A);
+ *  - D3Q15 (section "Extension to 3D" states 19 velocities are necessary
+ *    but gives no D3Q15 tables): weights with the second moments of
+ *    Appendix A and an isotropic leading error where a choice remains, the
+ *    corner weights of w^p, w^t, w^xx free (built in build_tables);
+ *  - the binary fluid and its walls (not defined by the paper): see the
+ *    binary section below.
  */
 #include <math.h>
 #include <stdlib.h>
@@ -48,7 +54,7 @@
 #endif
 
 typedef struct {
-    int q;          /* 9 = D2Q9, 19 = D3Q19 */
+    int q;          /* 9 = D2Q9, 19 = D3Q19, 15 = D3Q15 (lattice comparison) */
     int scheme;     /* 0 = tuned equilibrium, 1 = momentum-conserving force */
     int nx, ny, nz; /* nz = 1 for D2Q9 */
     int lambda_on;  /* 1 = include the Galilean-invariance lambda terms */
@@ -56,7 +62,7 @@ typedef struct {
     double B;       /* gradient stencil: off-axis coefficient */
     double D;       /* Laplacian stencil: off-axis coefficient */
     double F;       /* force stencil: off-axis coefficient */
-    double wp_d, wt_d, wxx_d; /* D2Q9 equilibrium weights on the diagonals */
+    double wp_d, wt_d, wxx_d; /* equilibrium weights on the D2Q9 diagonals (D3Q15: corners) */
 } orc_params;
 
 /* ---- velocity sets ------------------------------------------------------ */
