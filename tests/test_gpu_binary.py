@@ -294,20 +294,21 @@ def test_full_size_binary_matches_oracle_on_sampled_sites(name, q, shape, scheme
     sim.close()
 
 
-@pytest.mark.parametrize("scheme,wall", [(0, 0), (1, 1)])
-def test_full_size_binary_long_run_invariants(scheme, wall):
+@pytest.mark.parametrize("q,scheme,wall", [(19, 0, 0), (19, 1, 1), (15, 0, 0)])
+def test_full_size_binary_long_run_invariants(q, scheme, wall):
     """256^3 D3Q19 drop, 2000 steps in the autotuned launch: mass, order
     parameter and (periodic) momentum conserved to round-off, the state
     finite, the velocity small (the drop relaxes; no instability).  Also
-    the forcing scheme between walls, where the walls take up momentum."""
+    the forcing scheme between walls, where the walls take up momentum, and
+    D3Q15 at its stable corner weights."""
     from paper_0710_5470_amd import autotune, inputs
     lbm = _lbm()
     shape = (256, 256, 256)
     n = int(np.prod(shape))
-    gp, _ = _pair(19, shape, scheme=scheme, wall=wall)
+    gp, _ = _pair(q, shape, scheme=scheme, wall=wall, **(Q15 if q == 15 else {}))
     phi = inputs.tanh_drop(shape, 64.0, 1.0, -1.0, 2.0).reshape(-1)
     rho = 1.0 + inputs.uniform_noise(shape, 0.01, 41).reshape(-1)
-    _say("full-size binary long run 256^3 x 2000, scheme", scheme, "wall", wall)
+    _say("full-size binary long run 256^3 x 2000, q", q, "scheme", scheme, "wall", wall)
     sim = lbm.BinarySimulation(gp, rho, phi)
     autotune.autotune_binary(sim)
     m0, p0, j0 = sim.invariants()
