@@ -446,42 +446,50 @@ def _crossing(v):
     return k + v[k] / (v[k] - v[k + 1])
 
 
-@pytest.mark.parametrize("scheme", [0, 1])
-def test_drop_on_a_neutral_wall_relaxes_to_a_hemisphere(scheme):
+@pytest.mark.parametrize("q,scheme", [(19, 0), (19, 1), (9, 0), (9, 1)])
+def test_drop_on_a_neutral_wall_relaxes_to_a_hemisphere(q, scheme):
     """The mirrored stencils make the wall neutral: a drop centred on it
     relaxes to a hemisphere (contact angle 90 degrees), the half of the free
     drop in the periodic lattice of twice the depth holding the mirrored
     state.  Measured by the ratio of the drop's height along the wall normal
     to its radius along the wall (1 for a hemisphere, tan(theta / 2) for a
     cap of contact angle theta), against the same ratio of the free drop
-    (measured after 4000 steps: theta 89.6 deg and a ratio 0.007 from the
-    free drop's in the equilibrium scheme, 89.96 deg and 0.0003 in the
-    forcing scheme; near the contact line the equilibrium scheme keeps a
-    spurious velocity 5x the free drop's, to 40,000 steps at least)."""
+    (measured after 4000 steps: D3Q19 theta 89.6 deg and a ratio 0.007 from
+    the free drop's in the equilibrium scheme, 89.96 deg and 0.0003 in the
+    forcing scheme; D2Q9 89.1 deg and 0.017, 90.14 deg and 0.00003.  Near
+    the contact line the equilibrium scheme keeps a spurious velocity 5-7x
+    the free drop's, to 40,000 steps at least)."""
     lbm = _lbm()
     n, nz, R, steps = 48, 24, 12.0, 4000
     c = n // 2
-    z, y, x = np.meshgrid(np.arange(nz) + 0.5, np.arange(n), np.arange(n), indexing="ij")
-    phi_w = -np.tanh((np.sqrt((x - c) ** 2 + (y - c) ** 2 + z ** 2) - R) / 2.0)
+    if q == 9:   # the wall axis is y: a half disc
+        z, x = np.meshgrid(np.arange(nz) + 0.5, np.arange(n), indexing="ij")
+        dist = np.sqrt((x - c) ** 2 + z ** 2)
+    else:
+        z, y, x = np.meshgrid(np.arange(nz) + 0.5, np.arange(n), np.arange(n), indexing="ij")
+        dist = np.sqrt((x - c) ** 2 + (y - c) ** 2 + z ** 2)
+    phi_w = -np.tanh((dist - R) / 2.0)
     phi_p = np.concatenate([phi_w, phi_w[::-1]])     # planes 0..nz-1, then the mirror image
+    mid = (c,) * (phi_w.ndim - 2)                    # the centre in the in-plane axes other than x
     ratio = {}
-    for name, shape, wall, phi in (("walls", (n, n, nz), 1, phi_w), ("periodic", (n, n, 2 * nz), 0, phi_p)):
-        gp, _ = _pair(19, shape, wall=wall, scheme=scheme)
-        _say("drop on a wall:", name, shape, "scheme", scheme)
+    for name, wall, phi in (("walls", 1, phi_w), ("periodic", 0, phi_p)):
+        shape = phi.shape[::-1]
+        gp, _ = _pair(q, shape, wall=wall, scheme=scheme)
+        _say("drop on a wall:", name, shape, "q", q, "scheme", scheme)
         sim = lbm.BinarySimulation(gp, np.ones(phi.size), phi.reshape(-1))
         sim.step(steps)
-        ph = sim.moments()[1].cpu().numpy().reshape(shape[::-1])
+        ph = sim.moments()[1].cpu().numpy().reshape(phi.shape)
         umax = sim.max_spurious_u()
         sim.close()
         # height along the normal from the wall at -1/2 (periodic: from the
         # mirror plane between the last plane and plane 0), radius along x
         # on the plane next to the wall
-        h = _crossing(ph[:, c, c]) + 0.5
-        a = _crossing(ph[0, c, c:])
+        h = _crossing(ph[(slice(None),) + mid + (c,)]) + 0.5
+        a = _crossing(ph[(0,) + mid + (slice(c, None),)])
         ratio[name] = h / a
         _say(name, "height", h, "radius", a, "h/a", h / a, "max|u|", umax)
         assert np.isfinite(umax)
     theta = 2 * np.degrees(np.arctan(ratio["walls"]))
     _say("contact angle", theta, "deg")
-    assert abs(ratio["walls"] - ratio["periodic"]) < 2e-2
+    assert abs(ratio["walls"] - ratio["periodic"]) < 3e-2
     assert abs(theta - 90.0) < 2.0
